@@ -1,0 +1,202 @@
+"""Seeded synthetic circuit generators: the inputs shared by the oracle and the GPU path.
+
+This module produces circuit *descriptions* only: gate names from the canonical gate
+set of the paper's Section 3 (Eq. 4), qubit tuples, rotation angles, and, for Haar
+random single-qubit gates, the raw 2x2 unitary drawn from the seed (the paper's
+Section 8.1 workload of random U(2) gates).  It holds none of the simulation
+arithmetic: each consumer builds gate matrices from the names with its own code.
+
+Conventions
+-----------
+* Qubit t is bit t of the amplitude index (qubit 0 is the least significant bit),
+  as in the paper's Eq. 2 and Eq. 3.
+* A multi-qubit gate ``Op(name, (q0, q1, ...))`` orders its local basis index with
+  bit j <-> ``qubits[j]``.  CNOT(c, t) is ``Op("CNOT", (c, t))``, CZ is symmetric.
+* Parametric rotations carry ``param`` = index into a parameter vector; their
+  ``params`` tuple holds the bound angle.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+__all__ = [
+    "Op", "haar_u2", "brickwork", "ghz", "hea", "hea_params", "qft", "random_1q",
+    "tfim_terms", "zz_chain_terms", "x_sum_terms", "bind", "inverse_ops",
+    "serving_stream", "Request",
+]
+
+
+@dataclasses.dataclass(frozen=True)
+class Op:
+    name: str                      # canonical gate name (Eq. 4) or "U" for a raw unitary
+    qubits: Tuple[int, ...]
+    params: Tuple[float, ...] = ()
+    matrix: Optional[np.ndarray] = None   # only for name == "U" (complex128, 2^k x 2^k)
+    param: Optional[int] = None           # index into a parameter vector (rotations)
+
+
+def haar_u2(rng: np.random.Generator) -> np.ndarray:
+    """Haar-random U(2): QR of a complex Gaussian 2x2 with the phases of R's diagonal
+    moved into Q (Mezzadri's correction, without which plain QR is not Haar)."""
+    z = (rng.standard_normal((2, 2)) + 1j * rng.standard_normal((2, 2))) / math.sqrt(2.0)
+    q, r = np.linalg.qr(z)
+    d = np.diag(r)
+    q = q * (d / np.abs(d))[np.newaxis, :]
+    return np.ascontiguousarray(q, dtype=np.complex128)
+
+
+def brickwork(n: int, depth: int, seed: int) -> List[Op]:
+    """Random brickwork: every layer puts a Haar U(2) on each qubit (ascending), then
+    CNOT(2i, 2i+1) on even layers and CNOT(2i+1, 2i+2) on odd layers (control = lower
+    qubit).  Gate count = depth*n + sum of pairs per layer (290 at n=10, depth 20)."""
+    rng = np.random.default_rng(seed)
+    ops: List[Op] = []
+    for layer in range(depth):
+        for q in range(n):
+            ops.append(Op("U", (q,), matrix=haar_u2(rng)))
+        start = layer % 2
+        for c in range(start, n - 1, 2):
+            ops.append(Op("CNOT", (c, c + 1)))
+    return ops
+
+
+def ghz(n: int) -> List[Op]:
+    """H on qubit 0 then a CNOT chain (i, i+1): the GHZ state (the paper's Section 9.1)."""
+    ops = [Op("H", (0,))]
+    for i in range(n - 1):
+        ops.append(Op("CNOT", (i, i + 1)))
+    return ops
+
+
+def hea(n: int, layers: int, ring: bool = False, entangle: bool = True) -> List[Op]:
+    """Hardware-efficient ansatz template: per layer RY(theta) then RZ(phi) on every
+    qubit, then a CZ ladder (i, i+1) for i < n-1 (plus CZ(n-1, 0) when ``ring``).
+    Parameter order: layer -> qubit -> (theta, phi); 2*n*layers parameters.
+    Angles are unbound (params=()); use :func:`bind`."""
+    ops: List[Op] = []
+    p = 0
+    for _ in range(layers):
+        for q in range(n):
+            ops.append(Op("RY", (q,), param=p))
+            ops.append(Op("RZ", (q,), param=p + 1))
+            p += 2
+        if entangle:
+            for i in range(n - 1):
+                ops.append(Op("CZ", (i, i + 1)))
+            if ring and n > 2:
+                ops.append(Op("CZ", (n - 1, 0)))
+    return ops
+
+
+def hea_params(n: int, layers: int, seed: int, batch: Optional[int] = None) -> np.ndarray:
+    """Angles uniform in [0, 2*pi) drawn in the order layer -> qubit -> (theta, phi)."""
+    rng = np.random.default_rng(seed)
+    shape = (2 * n * layers,) if batch is None else (batch, 2 * n * layers)
+    return rng.uniform(0.0, 2.0 * math.pi, size=shape)
+
+
+def bind(ops: Sequence[Op], params: Sequence[float]) -> List[Op]:
+    """Fill each parametric op's angle from ``params[op.param]``."""
+    out = []
+    for op in ops:
+        if op.param is not None:
+            out.append(dataclasses.replace(op, params=(float(params[op.param]),)))
+        else:
+            out.append(op)
+    return out
+
+
+def qft(n: int) -> List[Op]:
+    """Textbook QFT without the final qubit reversal: for j = n-1 .. 0, H(j) then
+    controlled phases CP(pi/2^(j-k)) for k < j.  n + n(n-1)/2 gates (210 at n=20).
+    CP has no entry in Eq. 4, so it is emitted as its raw diagonal unitary."""
+    ops: List[Op] = []
+    for j in range(n - 1, -1, -1):
+        ops.append(Op("H", (j,)))
+        for k in range(j - 1, -1, -1):
+            lam = math.pi / (2 ** (j - k))
+            m = np.diag([1.0, 1.0, 1.0, complex(math.cos(lam), math.sin(lam))]).astype(np.complex128)
+            ops.append(Op("U", (k, j), matrix=m))
+    return ops
+
+
+def random_1q(n: int, seed: int, gates_per_qubit: int = 10) -> List[Op]:
+    """The paper's Section 8.1 workload: 10n Haar U(2) gates, each on a uniformly chosen qubit."""
+    rng = np.random.default_rng(seed)
+    ops = []
+    for _ in range(gates_per_qubit * n):
+        q = int(rng.integers(0, n))
+        ops.append(Op("U", (q,), matrix=haar_u2(rng)))
+    return ops
+
+
+def inverse_ops(ops: Sequence[Op]) -> List[Op]:
+    """The inverse circuit as raw data: reversed order, each named gate replaced by its
+    named inverse where one exists, raw unitaries by their conjugate transpose."""
+    inv = {"H": "H", "X": "X", "Y": "Y", "Z": "Z", "CNOT": "CNOT", "CZ": "CZ",
+           "SWAP": "SWAP", "TOFFOLI": "TOFFOLI", "I": "I", "S": "SDG", "SDG": "S",
+           "T": "TDG", "TDG": "T"}
+    out = []
+    for op in reversed(list(ops)):
+        if op.name == "U":
+            out.append(Op("U", op.qubits, matrix=np.ascontiguousarray(op.matrix.conj().T)))
+        elif op.name in ("RX", "RY", "RZ"):
+            out.append(Op(op.name, op.qubits, params=(-op.params[0],)))
+        elif op.name == "U3":
+            th, ph, lam = op.params
+            out.append(Op("U3", op.qubits, params=(-th, -lam, -ph)))
+        else:
+            out.append(Op(inv[op.name], op.qubits))
+    return out
+
+
+# ---------------------------------------------------------------- observables
+# A Pauli term is (coeff, ((qubit, 'X'|'Y'|'Z'), ...)).
+
+def zz_chain_terms(n: int, periodic: bool = False, coeff: float = 1.0):
+    terms = [(coeff, ((i, "Z"), (i + 1, "Z"))) for i in range(n - 1)]
+    if periodic and n > 2:
+        terms.append((coeff, ((n - 1, "Z"), (0, "Z"))))
+    return terms
+
+
+def x_sum_terms(n: int, coeff: float = 1.0):
+    return [(coeff, ((i, "X"),)) for i in range(n)]
+
+
+def tfim_terms(n: int, h: float = 0.7):
+    """Transverse-field Ising H = -sum Z_i Z_{i+1 mod n} - h sum X_i (periodic)."""
+    return zz_chain_terms(n, periodic=True, coeff=-1.0) + x_sum_terms(n, coeff=-h)
+
+
+# ---------------------------------------------------------------- serving stream
+
+@dataclasses.dataclass(frozen=True)
+class Request:
+    rid: int
+    arrival_s: float
+    n: int
+    depth: int
+    dtype: str          # "c64" or "c128"
+    seed: int
+
+
+def serving_stream(count: int = 4096, seed: int = 5, rate_hz: float = 200.0,
+                   n_lo: int = 12, n_hi: int = 26, d_lo: int = 10, d_hi: int = 60,
+                   p_c64: float = 0.7) -> List[Request]:
+    """Open-loop request stream: qubits uniform in [n_lo, n_hi], brickwork depth uniform
+    in [d_lo, d_hi], complex64 with probability p_c64, Poisson arrivals at rate_hz.
+    Each request's circuit is ``brickwork(n, depth, seed)`` with its own seed."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate_hz, size=count)
+    t = np.cumsum(gaps) - gaps[0]
+    ns = rng.integers(n_lo, n_hi + 1, size=count)
+    ds = rng.integers(d_lo, d_hi + 1, size=count)
+    c64 = rng.random(size=count) < p_c64
+    seeds = rng.integers(0, 2 ** 31 - 1, size=count)
+    return [Request(i, float(t[i]), int(ns[i]), int(ds[i]), "c64" if c64[i] else "c128",
+                    int(seeds[i])) for i in range(count)]
