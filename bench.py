@@ -1,0 +1,190 @@
+"""Benchmark of the state-vector hot path on one MI355X.
+
+One step = one pass of the hot path over one synthetic circuit already resident on the
+device: reset the state to |0...0>, apply the fused circuit (every HBM pass of the
+plan), then the reductions (norm and the <sum Z_i Z_i+1> expectation).  Planning is
+host work done once before the timed region and reported separately.
+
+Workload (headline): seeded random brickwork, 30 qubits, depth 20 (890 gates: a Haar
+U(2) on every qubit per layer, CNOT pairs alternating even/odd), complex64 state with
+FP32 arithmetic; the same circuit in complex128 is reported beside it.
+
+value = fused gates x 2 x 2^n x bytes-per-amplitude / step time  ("fused-gate amplitude
+GB/s": every fused gate must read and write each amplitude once; several fused gates
+share one HBM round trip, so the figure can exceed the HBM peak).
+
+roofline: the pass kernel.  Algorithmic bytes per launch = 2 x 2^n x bytes-per-amplitude
+(one read and one write of the state); the average launch duration comes from HIP
+events around single-pass launches on the state's stream.
+
+cpu_baseline: the FP64 CPU oracle (gate by gate, all host threads) on the first gates of
+the same 30-qubit circuit, reported in the same unit with its own (unfused) gate count.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-c128]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--qubits", type=int, default=30)
+    ap.add_argument("--depth", type=int, default=20)
+    ap.add_argument("--seed", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-c128", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    return ap.parse_args()
+
+
+def time_steps(torch, qsv, state, plan, terms, steps, warmup):
+    def step():
+        state.reset()
+        state.apply_plan(plan)
+        state.norm()
+        state.expval(terms)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def pass_durations(torch, state, plan, reps=2):
+    """Average device time of one pass launch, from HIP events on the state's stream."""
+    npass = plan.stats()["passes"]
+    stream = state.stream
+    times = []
+    for _ in range(reps):
+        evs = []
+        for i in range(npass):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            state.apply_plan(plan, i, 1)
+            b.record(stream)
+            evs.append((a, b))
+        torch.cuda.synchronize()
+        times += [a.elapsed_time(b) for a, b in evs]
+    return sum(times) / len(times)
+
+
+def run_dtype(torch, qsv, C, args, dtype, ops, terms):
+    n = args.qubits
+    t0 = time.perf_counter()
+    plan = qsv.Plan(n, dtype, ops)
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    st = plan.stats()
+    state = qsv.State(n, dtype)
+    sec = time_steps(torch, qsv, state, plan, terms, args.steps, args.warmup)
+    avg_pass_ms = pass_durations(torch, state, plan)
+    elem = 8 if dtype == "c64" else 16
+    pass_bytes = 2.0 * (2 ** n) * elem
+    value = st["fused_out"] * pass_bytes / sec / 1e9
+    achieved = pass_bytes / (avg_pass_ms * 1e-3) / 1e9
+    # sanity of the result: the circuit preserves the norm
+    norm = state.norm()
+    out = {
+        "value": value,
+        "ms_per_step": sec * 1e3,
+        "plan_ms": plan_ms,
+        "gates": st["gates_in"],
+        "fused_gates": st["fused_out"],
+        "passes": st["passes"],
+        "avg_pass_ms": avg_pass_ms,
+        "norm_minus_1": norm - 1.0,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+    }
+    state.free()
+    plan.free()
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(C, args, ops):
+    import numpy as np
+    import oracle
+    n = args.qubits
+    t0 = time.perf_counter()
+    psi = oracle.zero_state(n)
+    init_s = time.perf_counter() - t0
+    done, t_apply = 0, 0.0
+    while done < len(ops) and t_apply < args.cpu_seconds:
+        op = ops[done]
+        t1 = time.perf_counter()
+        oracle.apply(psi, oracle.op_matrix(op), op.qubits)
+        t_apply += time.perf_counter() - t1
+        done += 1
+    del psi
+    value = done * 2.0 * (2 ** n) * 16 / t_apply / 1e9
+    return {"value": value, "unit": "GB/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "first %d of %d gates of the %d-qubit depth-%d brickwork, complex128, gate by gate "
+                      "(%.1f s of gate application; state init %.1f s not counted)"
+                      % (done, len(ops), n, args.depth, t_apply, init_s)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the state-vector path here has no multi-GPU sharding "
+              "(see DESIGN.md for how it would shard); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2604_03816_amd import circuits as C
+    from paper_2604_03816_amd import qsv
+    if not os.path.exists(qsv.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    n = args.qubits
+    ops = C.brickwork(n, args.depth, args.seed)
+    terms = C.zz_chain_terms(n)
+    main_rec = run_dtype(torch, qsv, C, args, "c64", ops, terms)
+    rec = {
+        "metric": "fused-gate amplitude GB/s (% HBM peak) at 30q",
+        "value": main_rec["value"],
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_rec["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "brickwork n=%d depth=%d seed=%d complex64" % (n, args.depth, args.seed),
+                   "n_qubits": n, "depth": args.depth, "gates": main_rec["gates"],
+                   "fused_gates": main_rec["fused_gates"], "passes": main_rec["passes"],
+                   "state": "complex64"},
+        "roofline": main_rec["roofline"],
+        "detail": {k: main_rec[k] for k in ("plan_ms", "avg_pass_ms", "norm_minus_1")},
+    }
+    if not args.no_c128:
+        r = run_dtype(torch, qsv, C, args, "c128", ops, terms)
+        rec["c128"] = {"value": r["value"], "unit": "GB/s", "dtype": "f64", "ms_per_step": r["ms_per_step"],
+                       "fused_gates": r["fused_gates"], "passes": r["passes"], "avg_pass_ms": r["avg_pass_ms"],
+                       "roofline": r["roofline"], "norm_minus_1": r["norm_minus_1"]}
+    if not args.no_cpu:
+        rec["cpu_baseline"] = cpu_baseline(C, args, ops)
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

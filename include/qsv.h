@@ -1,0 +1,226 @@
+/*
+ * qsv.h -- C ABI of libqsv.so, an MI355X (gfx950) state-vector simulator core.
+ *
+ * The library applies circuits of k <= 5-qubit unitaries to a 2^n complex amplitude
+ * vector (the paper's problem statement: a gate sequence U_m ... U_1 applied to
+ * |0...0>, Section 3 and Eq. 5 / Eq. 10), after fusing the gate sequence on the host
+ * with the DAG fusion of Section 5.2 (Algorithm 2), and evaluates norm, probability
+ * and Pauli-expectation reductions over the vector.
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ * - Qubit t is bit t of the amplitude index (qubit 0 = least significant bit), as in
+ *   Eq. 2 and Eq. 3.  A state is 2^n contiguous complex numbers, real and imaginary
+ *   parts interleaved: complex64 (QSV_C64, 8 bytes) or complex128 (QSV_C128, 16 bytes).
+ * - A k-target matrix is row-major 2^k x 2^k complex128 given as 2*4^k doubles
+ *   (re, im interleaved); bit j of its row/column index belongs to targets[j].
+ * - Pointers named host_* or documented as host memory are CPU memory; the state
+ *   buffer and `out` buffers flagged as device memory are GPU memory.  The caller
+ *   owns every array it passes; the library copies what it needs before returning.
+ * - Every call returns a qsv_status; on failure nothing is modified (the state is
+ *   left untouched) and qsv_last_error() describes the failure.  No exception
+ *   crosses the ABI.
+ * - Device work is enqueued on the state's stream (a hipStream_t given at
+ *   qsv_alloc; NULL = the default stream).  qsv_apply_* return before the device
+ *   finishes; calls that return host results synchronise that stream.  Calls on one
+ *   state must not overlap from several host threads.
+ */
+#ifndef QSV_H
+#define QSV_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QSV_OK = 0,
+    QSV_E_ARG = 1,          /* invalid argument (targets, sizes, names, null pointers) */
+    QSV_E_OOM = 2,          /* device memory exhausted; nothing was allocated */
+    QSV_E_DEVICE = 3,       /* a HIP runtime call failed */
+    QSV_E_UNSUPPORTED = 4   /* valid request outside what this build supports */
+} qsv_status;
+
+typedef enum { QSV_C64 = 0, QSV_C128 = 1 } qsv_dtype;
+
+typedef struct qsv_state_s* qsv_state;   /* opaque */
+typedef struct qsv_plan_s* qsv_plan;     /* opaque */
+
+/* Thread-local message for the last failing call on this thread ("" if none). */
+const char* qsv_last_error(void);
+
+/* Library version string. */
+const char* qsv_version(void);
+
+/* ------------------------------------------------------------------ states */
+
+/* State-vector allocation and initialisation to |0...0> (Eq. 1 with alpha_0 = 1).
+ * n_qubits in [1, 34].  buf == NULL: the library allocates 2^n * elem bytes of device
+ * memory on the current HIP device and owns it.  buf != NULL: the library adopts the
+ * caller's device buffer (e.g. a torch tensor's data_ptr) of buf_bytes >= 2^n * elem
+ * bytes and never frees it.  stream: hipStream_t used for all device work on this
+ * state (NULL = default stream).  Errors: QSV_E_ARG (n out of range, buffer too small,
+ * out == NULL), QSV_E_OOM (allocation failed), QSV_E_DEVICE. */
+qsv_status qsv_alloc(int n_qubits, qsv_dtype dtype, void* buf, size_t buf_bytes,
+                     void* stream, qsv_state* out);
+
+/* Releases the state, its workspace and (if library-owned) its buffer after the
+ * state's stream has drained.  NULL is accepted. */
+qsv_status qsv_free(qsv_state s);
+
+/* Re-initialises the state to |0...0> (asynchronous). */
+qsv_status qsv_reset(qsv_state s);
+
+/* Queries: qubit count, dtype, device pointer of the amplitudes. */
+qsv_status qsv_info(qsv_state s, int* n_qubits, qsv_dtype* dtype, void** device_ptr);
+
+/* Copies the amplitudes to host memory host_out (2^n elements of the state's dtype);
+ * synchronises the stream. */
+qsv_status qsv_get_state(qsv_state s, void* host_out);
+
+/* Overwrites the amplitudes from host memory host_in (2^n elements of the state's
+ * dtype); synchronises the stream.  Used for checkpoint/restore and tests. */
+qsv_status qsv_set_state(qsv_state s, const void* host_in);
+
+/* ------------------------------------------------------------------ gates */
+
+/* One gate of a circuit (Section 3: a unitary, a tuple of targets).  k in [1, 5],
+ * targets distinct and < n.  mat: host pointer to 2*4^k doubles (dense) or, when
+ * diag != 0, to 2*2^k doubles holding only the diagonal. */
+typedef struct {
+    int k;
+    int targets[5];
+    int diag;
+    const double* mat;
+} qsv_gate;
+
+/* Canonical gate set of Eq. 4 (Section 3): "I","X","Y","Z","H","S","SDG","T","TDG",
+ * "RX","RY","RZ" (params[0] = theta, R_P(theta) = exp(-i theta P / 2)), "U3"
+ * (params = theta, phi, lambda; OpenQASM 2 convention), "CNOT" (local bit 0 = control),
+ * "CZ", "SWAP", "TOFFOLI" (local bits 0, 1 = controls).  Writes k and 2*4^k doubles
+ * into mat_out (capacity 2*64 doubles suffices).  QSV_E_ARG for an unknown name. */
+qsv_status qsv_gate_matrix(const char* name, const double* params, int* k, double* mat_out);
+
+/* ------------------------------------------------------------------ plans */
+
+/* Planner options.  Zero-initialise and set what you need; 0 selects the default. */
+typedef struct {
+    int fuse;            /* 0: no fusion, one gate per HBM pass (the plain path);
+                            1: DAG fusion (Algorithm 2) + multi-gate passes (default) */
+    int kmax;            /* fusion width q_max^fuse in [1, 5]; default 5 */
+    int cost_aware;      /* 1 (default): only fuse when the fused op costs no more
+                            arithmetic than its parts (Eq. 13 trade-off); -1: pure
+                            Algorithm 2 (fuse whenever the width allows) */
+    int tile_qubits;     /* log2 amplitudes per on-chip tile, 0 = default */
+    int low_qubits;      /* contiguous low qubits kept in every tile, 0 = default */
+    double pass_budget;  /* per-pass arithmetic budget (FMA per amplitude), 0 = default,
+                            < 0 = unlimited */
+} qsv_plan_opts;
+
+typedef struct {
+    size_t gates_in;       /* gates given */
+    size_t fused_out;      /* fused gates after DAG fusion */
+    size_t passes;         /* HBM passes (kernel launches) per application */
+    size_t dense_ops, diag_ops, perm_ops;
+    double fma_per_amp;    /* complex-arithmetic cost summed over all passes */
+    double hbm_bytes;      /* algorithmic HBM bytes per application = passes * 2 * 2^n * elem */
+} qsv_plan_stats;
+
+/* Fuses the gate list with Algorithm 2 (Section 5.2; Eq. 9 products in FP64; a fused
+ * gate is kept diagonal or as a generalised permutation when it is one) and
+ * schedules the fused gates into HBM passes.  Host-only: touches no device.  The
+ * plan is specific to (n_qubits, dtype).  opts may be NULL.  Errors: QSV_E_ARG. */
+qsv_status qsv_plan_create(int n_qubits, qsv_dtype dtype, const qsv_gate* gates,
+                           size_t n_gates, const qsv_plan_opts* opts, qsv_plan* out);
+qsv_status qsv_plan_free(qsv_plan p);
+qsv_status qsv_plan_get_stats(qsv_plan p, qsv_plan_stats* st);
+
+/* Fused gate i (in application order): k, sorted targets, diag flag and the dense
+ * 2^k x 2^k FP64 matrix (2*4^k doubles; mat may be NULL).  For host-side checking. */
+qsv_status qsv_plan_fused_gate(qsv_plan p, size_t i, int* k, int targets[5], int* diag,
+                               double* mat);
+
+/* Pass i: number of ops and the physical qubits held in its tile. */
+qsv_status qsv_plan_pass_info(qsv_plan p, size_t i, int* n_ops, int* n_active,
+                              int active[40]);
+
+/* Pass i, in application order: the indices (into the fused-gate list) of its ops, in
+ * the order the pass applies them.  fused_idx must hold n_ops ints. */
+qsv_status qsv_plan_pass_ops(qsv_plan p, size_t i, int* fused_idx);
+
+/* Enqueues the plan's passes on the state's stream (Eq. 10: the fused product applied
+ * in order).  The plan must match the state's n and dtype.  The plan may be freed
+ * only after the stream has finished with it (qsv_sync). */
+qsv_status qsv_plan_apply(qsv_state s, qsv_plan p);
+
+/* Enqueues only passes [first, first+count) of the plan (for timing single passes). */
+qsv_status qsv_plan_apply_range(qsv_state s, qsv_plan p, size_t first, size_t count);
+
+/* One call = plan + apply + release; synchronises the stream before returning.
+ * stats may be NULL. */
+qsv_status qsv_apply_fused(qsv_state s, const qsv_gate* gates, size_t n_gates,
+                           const qsv_plan_opts* opts, qsv_plan_stats* stats);
+
+/* Waits for all work enqueued on the state's stream. */
+qsv_status qsv_sync(qsv_state s);
+
+/* ------------------------------------------------------------------ reductions */
+
+/* sum_k |alpha_k|^2 (Eq. 1 normalisation), accumulated in FP64 per thread, combined
+ * with Neumaier's compensated sum in a fixed order (deterministic).  Synchronous. */
+qsv_status qsv_norm(qsv_state s, double* out);
+
+/* One Pauli-sum term: coeff * prod_j sigma_{paulis[j]}(qubits[j]), paulis in "IXYZ",
+ * n Pauli factors on distinct qubits.  qubits/paulis are host arrays. */
+typedef struct {
+    double coeff;
+    int n;
+    const int* qubits;
+    const char* paulis;
+} qsv_pauli_term;
+
+/* <psi|P_t|psi> for every term (Hermitian Pauli strings, real result), evaluated in
+ * as few read passes over the state as the terms allow, FP64 accumulation with a
+ * compensated, fixed-order combination.  per_term (host, n_terms doubles) receives
+ * coeff_t * <P_t>; sum (host) receives their compensated sum.  Either may be NULL.
+ * Synchronous.  Errors: QSV_E_ARG for bad qubits or letters. */
+qsv_status qsv_expval_pauli(qsv_state s, const qsv_pauli_term* terms, size_t n_terms,
+                            double* per_term, double* sum);
+
+/* Outcome probabilities (Eq. 1 and Eq. 18).  m == n and qubits == NULL or (0..n-1):
+ * the full distribution |alpha_k|^2, written in the state's real precision (float
+ * for C64, double for C128).  Otherwise the marginal over `qubits` (m distinct
+ * qubits, output index bit j <-> qubits[j]) written as 2^m doubles accumulated in
+ * FP64.  out is device memory when out_on_device != 0, else host memory (then the
+ * call synchronises).  Errors: QSV_E_ARG. */
+qsv_status qsv_probs(qsv_state s, const int* qubits, int m, void* out, int out_on_device);
+
+/* ------------------------------------------------------------------ gradients */
+
+/* One op of a parameterised circuit.  kind 0: fixed gate (k, targets, mat as in
+ * qsv_gate with diag = 0).  kind 1/2/3: RX/RY/RZ(params[b*P + param]) on targets[0]
+ * (R_P(theta) = exp(-i theta P / 2), Eq. 4). */
+typedef struct {
+    int kind;
+    int k;
+    int targets[5];
+    const double* mat;
+    int param;
+} qsv_op;
+
+/* Energies E_b = <psi_b|H|psi_b>, psi_b = U(theta_b)|0...0>, and their gradients
+ * dE_b/dtheta_j by the adjoint method (one forward sweep, one reverse sweep that
+ * uncomputes the state and the co-state layer by layer).  params: host, B x P
+ * row-major doubles.  energy: host, B doubles; grad: host, B x P doubles (entries of
+ * parameters no op uses are 0).  Runs on `stream` (hipStream_t, NULL = default) and
+ * synchronises it.  Errors: QSV_E_ARG, QSV_E_OOM, QSV_E_DEVICE. */
+qsv_status qsv_adjoint_grad(int n_qubits, qsv_dtype dtype, const qsv_op* ops, size_t n_ops,
+                            const double* params, int B, int P,
+                            const qsv_pauli_term* H, size_t n_terms,
+                            double* energy, double* grad, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QSV_H */

@@ -1,0 +1,928 @@
+// capi.cpp -- the extern "C" boundary of libqsv.so (declared in include/qsv.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/qsv.h"
+#include "planner.h"
+#include "qsv_internal.h"
+
+using namespace qsv;
+
+namespace {
+
+thread_local std::string g_err;
+
+qsv_status fail(qsv_status st, const std::string& msg)
+{
+    g_err = msg;
+    return st;
+}
+
+#define QSV_HIP(call)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess) return fail(QSV_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t elem_bytes(int dtype) { return dtype == QSV_C64 ? 8 : 16; }
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+struct qsv_state_s {
+    int n = 0;
+    int dtype = 0;
+    void* buf = nullptr;
+    bool owned = false;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    // reduction workspace (device) and its host mirror (pinned)
+    double* d_work = nullptr;
+    size_t work_bytes = 0;
+    double* h_work = nullptr;
+    size_t hwork_bytes = 0;
+};
+
+struct qsv_plan_s {
+    HostPlan hp;
+    int device = -1;
+    DevOp* d_ops = nullptr;
+    void* d_pool = nullptr;
+    int* d_ipool = nullptr;
+};
+
+namespace {
+
+qsv_status ensure_work(qsv_state s, size_t bytes)
+{
+    if (bytes <= s->work_bytes) return QSV_OK;
+    if (s->d_work) {
+        QSV_HIP(hipStreamSynchronize(s->stream));
+        QSV_HIP(hipFree(s->d_work));
+        s->d_work = nullptr;
+        s->work_bytes = 0;
+    }
+    const size_t want = std::max<size_t>(bytes, 1 << 16);
+    if (hipMalloc((void**)&s->d_work, want) != hipSuccess) {
+        (void)hipGetLastError();
+        s->d_work = nullptr;
+        return fail(QSV_E_OOM, "workspace allocation failed");
+    }
+    s->work_bytes = want;
+    return QSV_OK;
+}
+
+qsv_status ensure_hwork(qsv_state s, size_t bytes)
+{
+    if (bytes <= s->hwork_bytes) return QSV_OK;
+    if (s->h_work) {
+        QSV_HIP(hipHostFree(s->h_work));
+        s->h_work = nullptr;
+        s->hwork_bytes = 0;
+    }
+    const size_t want = std::max<size_t>(bytes, 1 << 16);
+    QSV_HIP(hipHostMalloc((void**)&s->h_work, want, hipHostMallocDefault));
+    s->hwork_bytes = want;
+    return QSV_OK;
+}
+
+struct NS {
+    double s = 0, c = 0;
+    void add(double x)
+    {
+        const double t = s + x;
+        c += (std::fabs(s) >= std::fabs(x)) ? ((s - t) + x) : ((x - t) + s);
+        s = t;
+    }
+    double value() const { return s + c; }
+};
+
+qsv_status check_state(qsv_state s)
+{
+    if (!s) return fail(QSV_E_ARG, "null state");
+    return QSV_OK;
+}
+
+bool read_gate(const qsv_gate& g, int n, InGate& out, std::string& err)
+{
+    if (g.k < 1 || g.k > kMaxK) { err = "gate k must be in [1, 5]"; return false; }
+    for (int j = 0; j < g.k; ++j) {
+        if (g.targets[j] < 0 || g.targets[j] >= n) { err = "gate target out of range"; return false; }
+        for (int i = 0; i < j; ++i)
+            if (g.targets[i] == g.targets[j]) { err = "duplicate gate target"; return false; }
+    }
+    if (!g.mat) { err = "null gate matrix"; return false; }
+    out.k = g.k;
+    for (int j = 0; j < kMaxK; ++j) out.t[j] = j < g.k ? g.targets[j] : 0;
+    const int d = 1 << g.k;
+    out.m.assign((size_t)d * d, cd(0, 0));
+    if (g.diag) {
+        for (int r = 0; r < d; ++r) out.m[(size_t)r * d + r] = cd(g.mat[2 * r], g.mat[2 * r + 1]);
+    } else {
+        for (int i = 0; i < d * d; ++i) out.m[i] = cd(g.mat[2 * i], g.mat[2 * i + 1]);
+    }
+    for (const cd& v : out.m)
+        if (!std::isfinite(v.real()) || !std::isfinite(v.imag())) { err = "non-finite gate matrix entry"; return false; }
+    return true;
+}
+
+qsv_status upload_plan(qsv_plan p, int device)
+{
+    if (p->device == device) return QSV_OK;
+    if (p->device >= 0) {
+        DeviceGuard g(p->device);
+        (void)hipFree(p->d_ops);
+        (void)hipFree(p->d_pool);
+        (void)hipFree(p->d_ipool);
+        p->d_ops = nullptr;
+        p->d_pool = nullptr;
+        p->d_ipool = nullptr;
+        p->device = -1;
+    }
+    const HostPlan& hp = p->hp;
+    const size_t nops = std::max<size_t>(hp.ops.size(), 1);
+    const size_t npool = std::max<size_t>(hp.pool.size(), 1);
+    const size_t nipool = std::max<size_t>(hp.ipool.size(), 1);
+    const size_t eb = elem_bytes(hp.dtype);
+    if (hipMalloc((void**)&p->d_ops, nops * sizeof(DevOp)) != hipSuccess ||
+        hipMalloc(&p->d_pool, npool * eb) != hipSuccess ||
+        hipMalloc((void**)&p->d_ipool, nipool * sizeof(int)) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(p->d_ops);
+        (void)hipFree(p->d_pool);
+        (void)hipFree(p->d_ipool);
+        p->d_ops = nullptr;
+        p->d_pool = nullptr;
+        p->d_ipool = nullptr;
+        return fail(QSV_E_OOM, "plan table allocation failed");
+    }
+    std::vector<unsigned char> pool(npool * eb, 0);
+    for (size_t i = 0; i < hp.pool.size(); ++i) {
+        if (hp.dtype == QSV_C64) {
+            float* f = reinterpret_cast<float*>(pool.data()) + 2 * i;
+            f[0] = (float)hp.pool[i].real();
+            f[1] = (float)hp.pool[i].imag();
+        } else {
+            double* f = reinterpret_cast<double*>(pool.data()) + 2 * i;
+            f[0] = hp.pool[i].real();
+            f[1] = hp.pool[i].imag();
+        }
+    }
+    if (!hp.ops.empty()) QSV_HIP(hipMemcpy(p->d_ops, hp.ops.data(), hp.ops.size() * sizeof(DevOp), hipMemcpyHostToDevice));
+    QSV_HIP(hipMemcpy(p->d_pool, pool.data(), pool.size(), hipMemcpyHostToDevice));
+    if (!hp.ipool.empty()) QSV_HIP(hipMemcpy(p->d_ipool, hp.ipool.data(), hp.ipool.size() * sizeof(int), hipMemcpyHostToDevice));
+    p->device = device;
+    return QSV_OK;
+}
+
+// Parsed Pauli term: X/Y mask, Z/Y mask, number of Y factors.
+struct PTerm {
+    unsigned long long x = 0, z = 0;
+    int ny = 0;
+    double coeff = 0;
+};
+
+bool parse_terms(const qsv_pauli_term* terms, size_t nt, int n, std::vector<PTerm>& out, std::string& err)
+{
+    out.resize(nt);
+    for (size_t i = 0; i < nt; ++i) {
+        const qsv_pauli_term& t = terms[i];
+        PTerm p;
+        p.coeff = t.coeff;
+        if (t.n < 0 || (t.n > 0 && (!t.qubits || !t.paulis))) { err = "bad Pauli term"; return false; }
+        for (int j = 0; j < t.n; ++j) {
+            const int q = t.qubits[j];
+            if (q < 0 || q >= n) { err = "Pauli qubit out of range"; return false; }
+            const unsigned long long b = 1ull << q;
+            if ((p.x | p.z) & b) { err = "repeated qubit in a Pauli term"; return false; }
+            switch (t.paulis[j]) {
+            case 'I': break;
+            case 'X': p.x |= b; break;
+            case 'Y': p.x |= b; p.z |= b; ++p.ny; break;
+            case 'Z': p.z |= b; break;
+            default: err = "Pauli letters must be I, X, Y or Z"; return false;
+            }
+        }
+        out[i] = p;
+    }
+    return true;
+}
+
+// Tile geometry for a set of must-have qubits: the low L qubits plus `need`, filled
+// with the lowest other qubits up to m.
+PassArgs tile_args(int n, int m, int L, unsigned long long need, std::vector<int>& active)
+{
+    unsigned long long A = need;
+    for (int b = 0; b < L && b < n; ++b) A |= 1ull << b;
+    for (int b = 0; b < n && __builtin_popcountll(A) < m; ++b) A |= 1ull << b;
+    active.clear();
+    for (int b = 0; b < n; ++b)
+        if ((A >> b) & 1) active.push_back(b);
+    PassArgs a{};
+    a.m = (int)active.size();
+    a.L = std::min(L, a.m);
+    for (int i = a.L; i < a.m; ++i) a.hstride[i - a.L] = 1ll << active[i];
+    int b = 0;
+    while (b < n) {
+        if ((A >> b) & 1) { ++b; continue; }
+        const int s = b;
+        while (b < n && !((A >> b) & 1)) ++b;
+        a.run_pos[a.nruns] = s;
+        a.run_len[a.nruns] = b - s;
+        ++a.nruns;
+    }
+    return a;
+}
+
+// out[i] = Re <a|P_i|b> (imag == false) or Im <a|P_i|b> (imag == true), unweighted, for
+// states a and b of s's shape (a == b for expectation values).  Terms are grouped so
+// that each group's X/Y supports fit one tile; one read pass per group.
+qsv_status pauli_elements(qsv_state s, const void* sa, const void* sb, const std::vector<PTerm>& terms, bool imag,
+                          std::vector<double>& out)
+{
+    const int n = s->n;
+    const PlanOpts o = default_opts(s->dtype);
+    // tiles of at most 32 KiB leave room for the kernel's static reduction scratch
+    const int m = std::min(n, s->dtype == QSV_C64 ? 12 : 11);
+    const int L = std::min(o.low_qubits, m);
+    const unsigned long long lowmask = (L >= 64) ? ~0ull : ((1ull << L) - 1);
+    out.assign(terms.size(), 0.0);
+    std::vector<std::vector<int>> groups;
+    std::vector<unsigned long long> gneed;
+    for (size_t i = 0; i < terms.size(); ++i) {
+        const unsigned long long x = terms[i].x;
+        if (__builtin_popcountll(x | lowmask) > m)
+            return fail(QSV_E_UNSUPPORTED, "Pauli term flips more qubits than one tile holds");
+        bool placed = false;
+        for (size_t g = 0; g < groups.size() && !placed; ++g) {
+            const unsigned long long need = gneed[g] | x;
+            if (groups[g].size() < (size_t)kMaxTermsPerLaunch && __builtin_popcountll(need | lowmask) <= m) {
+                groups[g].push_back((int)i);
+                gneed[g] = need;
+                placed = true;
+            }
+        }
+        if (!placed) {
+            groups.push_back({(int)i});
+            gneed.push_back(x);
+        }
+    }
+    for (size_t g = 0; g < groups.size(); ++g) {
+        std::vector<int> active;
+        const PassArgs a = tile_args(n, m, L, gneed[g], active);
+        TermArgs ta{};
+        ta.nterms = (int)groups[g].size();
+        for (int i = 0; i < ta.nterms; ++i) {
+            const PTerm& p = terms[groups[g][i]];
+            int xl = 0, zl = 0;
+            unsigned long long zg = p.z;
+            for (int j = 0; j < a.m; ++j) {
+                const unsigned long long b = 1ull << active[j];
+                if (p.x & b) xl |= 1 << j;
+                if (p.z & b) { zl |= 1 << j; zg &= ~b; }
+            }
+            ta.xloc[i] = xl;
+            ta.zloc[i] = zl;
+            ta.zglob[i] = (long long)zg;
+            ta.ny[i] = p.ny + (imag ? 3 : 0);   // Im z = Re(-i z), and -i = i^3
+        }
+        const long long ntiles = 1ll << (n - a.m);
+        const int grid = (int)std::min<long long>(ntiles, 1024);
+        const size_t bytes = (size_t)grid * ta.nterms * 2 * sizeof(double);
+        qsv_status st = ensure_work(s, bytes);
+        if (st != QSV_OK) return st;
+        st = ensure_hwork(s, bytes);
+        if (st != QSV_OK) return st;
+        QSV_HIP(launch_expval(s->dtype, sa, sb, a, ta, ntiles, grid, s->d_work, s->stream));
+        QSV_HIP(hipMemcpyAsync(s->h_work, s->d_work, bytes, hipMemcpyDeviceToHost, s->stream));
+        QSV_HIP(hipStreamSynchronize(s->stream));
+        for (int i = 0; i < ta.nterms; ++i) {
+            NS acc;
+            for (int b = 0; b < grid; ++b) {
+                acc.add(s->h_work[((size_t)b * ta.nterms + i) * 2]);
+                acc.c += s->h_work[((size_t)b * ta.nterms + i) * 2 + 1];
+            }
+            out[groups[g][i]] = acc.value();
+        }
+    }
+    return QSV_OK;
+}
+
+qsv_status expval_core(qsv_state s, const std::vector<PTerm>& terms, std::vector<double>& out)
+{
+    return pauli_elements(s, s->buf, s->buf, terms, false, out);
+}
+
+// dst = sum_t coeff_t P_t src, terms in batches of kMaxPauliApply launches.
+qsv_status pauli_sum_apply(qsv_state s, const void* src, void* dst, const std::vector<PTerm>& terms)
+{
+    const long long N = 1ll << s->n;
+    if (terms.empty()) {
+        QSV_HIP(launch_zero(s->dtype, dst, N, s->stream));
+        return QSV_OK;
+    }
+    for (size_t b = 0; b < terms.size(); b += kMaxPauliApply) {
+        PauliSumArgs p{};
+        p.nterms = (int)std::min<size_t>(kMaxPauliApply, terms.size() - b);
+        for (int i = 0; i < p.nterms; ++i) {
+            const PTerm& t = terms[b + i];
+            p.x[i] = (long long)t.x;
+            p.z[i] = (long long)t.z;
+            p.ny[i] = t.ny;
+            p.coeff[i] = t.coeff;
+        }
+        QSV_HIP(launch_pauli_apply(s->dtype, src, dst, N, p, b > 0 ? 1 : 0, s->stream));
+    }
+    return QSV_OK;
+}
+
+// Plans and enqueues `gates` on a state (the plan is released after the stream drains).
+qsv_status apply_gates(qsv_state s, const std::vector<InGate>& gates)
+{
+    if (gates.empty()) return QSV_OK;
+    PlanOpts o = default_opts(s->dtype);
+    qsv_plan p = new qsv_plan_s();
+    std::string err;
+    if (!make_plan(s->n, s->dtype, gates, o, p->hp, err)) {
+        delete p;
+        return fail(QSV_E_ARG, err);
+    }
+    qsv_status st = upload_plan(p, s->device);
+    for (size_t i = 0; st == QSV_OK && i < p->hp.passes.size(); ++i) {
+        const hipError_t e = launch_pass(s->dtype, s->buf, p->hp.pargs[i], p->hp.pgrid[i], p->d_ops, p->d_pool,
+                                         p->d_ipool, s->stream);
+        if (e != hipSuccess) st = fail(QSV_E_DEVICE, std::string("pass: ") + hipGetErrorString(e));
+    }
+    const hipError_t e = hipStreamSynchronize(s->stream);
+    if (p->device >= 0) {
+        (void)hipFree(p->d_ops);
+        (void)hipFree(p->d_pool);
+        (void)hipFree(p->d_ipool);
+    }
+    delete p;
+    if (st == QSV_OK && e != hipSuccess) return fail(QSV_E_DEVICE, std::string("apply: ") + hipGetErrorString(e));
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* qsv_last_error(void) { return g_err.c_str(); }
+
+const char* qsv_version(void) { return "qsv 0.1 (gfx950)"; }
+
+qsv_status qsv_alloc(int n, qsv_dtype dtype, void* buf, size_t buf_bytes, void* stream, qsv_state* out)
+{
+    if (!out) return fail(QSV_E_ARG, "out is null");
+    *out = nullptr;
+    if (n < 1 || n > kMaxQubits) return fail(QSV_E_ARG, "n_qubits must be in [1, 34]");
+    if (dtype != QSV_C64 && dtype != QSV_C128) return fail(QSV_E_ARG, "bad dtype");
+    const size_t bytes = elem_bytes(dtype) << n;
+    if (buf && buf_bytes < bytes) return fail(QSV_E_ARG, "adopted buffer is smaller than 2^n amplitudes");
+    int dev = 0;
+    QSV_HIP(hipGetDevice(&dev));
+    qsv_state s = new qsv_state_s();
+    s->n = n;
+    s->dtype = dtype;
+    s->stream = (hipStream_t)stream;
+    s->device = dev;
+    if (buf) {
+        s->buf = buf;
+    } else {
+        if (hipMalloc(&s->buf, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            delete s;
+            return fail(QSV_E_OOM, "state allocation of " + std::to_string(bytes) + " bytes failed");
+        }
+        s->owned = true;
+    }
+    hipError_t e = launch_init_zero(dtype, s->buf, 1ll << n, s->stream);
+    if (e != hipSuccess) {
+        if (s->owned) (void)hipFree(s->buf);
+        delete s;
+        return fail(QSV_E_DEVICE, std::string("init: ") + hipGetErrorString(e));
+    }
+    *out = s;
+    return QSV_OK;
+}
+
+qsv_status qsv_free(qsv_state s)
+{
+    if (!s) return QSV_OK;
+    DeviceGuard g(s->device);
+    (void)hipStreamSynchronize(s->stream);
+    if (s->owned) (void)hipFree(s->buf);
+    if (s->d_work) (void)hipFree(s->d_work);
+    if (s->h_work) (void)hipHostFree(s->h_work);
+    delete s;
+    return QSV_OK;
+}
+
+qsv_status qsv_reset(qsv_state s)
+{
+    qsv_status st = check_state(s);
+    if (st != QSV_OK) return st;
+    DeviceGuard g(s->device);
+    QSV_HIP(launch_init_zero(s->dtype, s->buf, 1ll << s->n, s->stream));
+    return QSV_OK;
+}
+
+qsv_status qsv_info(qsv_state s, int* n, qsv_dtype* dtype, void** ptr)
+{
+    qsv_status st = check_state(s);
+    if (st != QSV_OK) return st;
+    if (n) *n = s->n;
+    if (dtype) *dtype = (qsv_dtype)s->dtype;
+    if (ptr) *ptr = s->buf;
+    return QSV_OK;
+}
+
+qsv_status qsv_get_state(qsv_state s, void* host_out)
+{
+    qsv_status st = check_state(s);
+    if (st != QSV_OK) return st;
+    if (!host_out) return fail(QSV_E_ARG, "host_out is null");
+    DeviceGuard g(s->device);
+    QSV_HIP(hipMemcpyAsync(host_out, s->buf, elem_bytes(s->dtype) << s->n, hipMemcpyDeviceToHost, s->stream));
+    QSV_HIP(hipStreamSynchronize(s->stream));
+    return QSV_OK;
+}
+
+qsv_status qsv_set_state(qsv_state s, const void* host_in)
+{
+    qsv_status st = check_state(s);
+    if (st != QSV_OK) return st;
+    if (!host_in) return fail(QSV_E_ARG, "host_in is null");
+    DeviceGuard g(s->device);
+    QSV_HIP(hipMemcpyAsync(s->buf, host_in, elem_bytes(s->dtype) << s->n, hipMemcpyHostToDevice, s->stream));
+    QSV_HIP(hipStreamSynchronize(s->stream));
+    return QSV_OK;
+}
+
+qsv_status qsv_sync(qsv_state s)
+{
+    qsv_status st = check_state(s);
+    if (st != QSV_OK) return st;
+    DeviceGuard g(s->device);
+    QSV_HIP(hipStreamSynchronize(s->stream));
+    return QSV_OK;
+}
+
+// Eq. 4 gate set, written from the definitions: rotations exp(-i theta P / 2),
+// U3 in the OpenQASM 2 convention, multi-qubit gates by their basis action.
+qsv_status qsv_gate_matrix(const char* name, const double* p, int* k, double* mat)
+{
+    if (!name || !k || !mat) return fail(QSV_E_ARG, "null argument");
+    const std::string nm(name);
+    const bool needs1 = nm == "RX" || nm == "RY" || nm == "RZ", needs3 = nm == "U3";
+    if ((needs1 || needs3) && !p) return fail(QSV_E_ARG, "missing gate parameters");
+    std::vector<cd> U;
+    int kk = 1;
+    const cd i1(0, 1);
+    if (nm == "I") U = {1, 0, 0, 1};
+    else if (nm == "X") U = {0, 1, 1, 0};
+    else if (nm == "Y") U = {0, -i1, i1, 0};
+    else if (nm == "Z") U = {1, 0, 0, -1};
+    else if (nm == "H") { const double h = 1.0 / std::sqrt(2.0); U = {h, h, h, -h}; }
+    else if (nm == "S") U = {1, 0, 0, i1};
+    else if (nm == "SDG") U = {1, 0, 0, -i1};
+    else if (nm == "T") U = {1, 0, 0, std::polar(1.0, M_PI / 4)};
+    else if (nm == "TDG") U = {1, 0, 0, std::polar(1.0, -M_PI / 4)};
+    else if (nm == "RX") { const double c = std::cos(p[0] / 2), s = std::sin(p[0] / 2); U = {c, -i1 * s, -i1 * s, c}; }
+    else if (nm == "RY") { const double c = std::cos(p[0] / 2), s = std::sin(p[0] / 2); U = {c, -s, s, c}; }
+    else if (nm == "RZ") U = {std::polar(1.0, -p[0] / 2), 0, 0, std::polar(1.0, p[0] / 2)};
+    else if (nm == "U3") {
+        const double c = std::cos(p[0] / 2), s = std::sin(p[0] / 2);
+        U = {c, -std::polar(1.0, p[2]) * s, std::polar(1.0, p[1]) * s, std::polar(1.0, p[1] + p[2]) * c};
+    } else if (nm == "CNOT" || nm == "CZ" || nm == "SWAP" || nm == "TOFFOLI") {
+        kk = nm == "TOFFOLI" ? 3 : 2;
+        const int d = 1 << kk;
+        U.assign((size_t)d * d, 0);
+        for (int in = 0; in < d; ++in) {
+            int outi = in;
+            cd amp = 1;
+            if (nm == "CNOT" && (in & 1)) outi = in ^ 2;
+            if (nm == "CZ" && in == 3) amp = -1;
+            if (nm == "SWAP") outi = ((in & 1) << 1) | ((in >> 1) & 1);
+            if (nm == "TOFFOLI" && (in & 3) == 3) outi = in ^ 4;
+            U[(size_t)outi * d + in] = amp;
+        }
+    } else {
+        return fail(QSV_E_ARG, "unknown gate name " + nm);
+    }
+    *k = kk;
+    for (size_t i = 0; i < U.size(); ++i) {
+        mat[2 * i] = U[i].real();
+        mat[2 * i + 1] = U[i].imag();
+    }
+    return QSV_OK;
+}
+
+qsv_status qsv_plan_create(int n, qsv_dtype dtype, const qsv_gate* gates, size_t n_gates,
+                           const qsv_plan_opts* opts, qsv_plan* out)
+{
+    if (!out) return fail(QSV_E_ARG, "out is null");
+    *out = nullptr;
+    if (n < 1 || n > kMaxQubits) return fail(QSV_E_ARG, "n_qubits must be in [1, 34]");
+    if (dtype != QSV_C64 && dtype != QSV_C128) return fail(QSV_E_ARG, "bad dtype");
+    if (n_gates && !gates) return fail(QSV_E_ARG, "gates is null");
+    PlanOpts o = default_opts(dtype);
+    if (opts) {
+        o.fuse = opts->fuse;
+        if (opts->kmax) o.kmax = opts->kmax;
+        if (opts->cost_aware) o.cost_aware = opts->cost_aware;
+        if (opts->tile_qubits) o.tile_qubits = opts->tile_qubits;
+        if (opts->low_qubits) o.low_qubits = opts->low_qubits;
+        if (opts->pass_budget != 0) o.pass_budget = opts->pass_budget;
+    }
+    if (!o.fuse) o.max_ops_per_pass = 1;
+    const int max_tile = dtype == QSV_C64 ? 13 : 12;   // 64 KiB of LDS
+    if (o.tile_qubits > max_tile) return fail(QSV_E_ARG, "tile_qubits exceeds the LDS tile limit");
+    std::vector<InGate> in(n_gates);
+    std::string err;
+    for (size_t i = 0; i < n_gates; ++i)
+        if (!read_gate(gates[i], n, in[i], err)) return fail(QSV_E_ARG, "gate " + std::to_string(i) + ": " + err);
+    qsv_plan p = new qsv_plan_s();
+    if (!make_plan(n, dtype, in, o, p->hp, err)) {
+        delete p;
+        return fail(QSV_E_ARG, err);
+    }
+    *out = p;
+    return QSV_OK;
+}
+
+qsv_status qsv_plan_free(qsv_plan p)
+{
+    if (!p) return QSV_OK;
+    if (p->device >= 0) {
+        DeviceGuard g(p->device);
+        (void)hipFree(p->d_ops);
+        (void)hipFree(p->d_pool);
+        (void)hipFree(p->d_ipool);
+    }
+    delete p;
+    return QSV_OK;
+}
+
+qsv_status qsv_plan_get_stats(qsv_plan p, qsv_plan_stats* st)
+{
+    if (!p || !st) return fail(QSV_E_ARG, "null argument");
+    const HostPlan& hp = p->hp;
+    st->gates_in = hp.gates_in;
+    st->fused_out = hp.fused.size();
+    st->passes = hp.passes.size();
+    st->dense_ops = hp.dense_ops;
+    st->diag_ops = hp.diag_ops;
+    st->perm_ops = hp.perm_ops;
+    st->fma_per_amp = hp.fma_per_amp;
+    st->hbm_bytes = (double)hp.passes.size() * 2.0 * (double)(elem_bytes(hp.dtype) << hp.n);
+    return QSV_OK;
+}
+
+qsv_status qsv_plan_fused_gate(qsv_plan p, size_t i, int* k, int targets[5], int* diag, double* mat)
+{
+    if (!p || !k || !targets || !diag) return fail(QSV_E_ARG, "null argument");
+    if (i >= p->hp.fused.size()) return fail(QSV_E_ARG, "fused gate index out of range");
+    const FGate& g = p->hp.fused[i];
+    *k = g.k;
+    for (int j = 0; j < 5; ++j) targets[j] = j < g.k ? g.q[j] : -1;
+    *diag = g.kind == OP_DIAG;
+    if (mat)
+        for (size_t e = 0; e < g.m.size(); ++e) {
+            mat[2 * e] = g.m[e].real();
+            mat[2 * e + 1] = g.m[e].imag();
+        }
+    return QSV_OK;
+}
+
+qsv_status qsv_plan_pass_info(qsv_plan p, size_t i, int* n_ops, int* n_active, int active[40])
+{
+    if (!p || !n_ops || !n_active || !active) return fail(QSV_E_ARG, "null argument");
+    if (i >= p->hp.passes.size()) return fail(QSV_E_ARG, "pass index out of range");
+    const PassPlan& pp = p->hp.passes[i];
+    *n_ops = (int)pp.ops.size();
+    *n_active = (int)pp.active.size();
+    for (size_t j = 0; j < pp.active.size(); ++j) active[j] = pp.active[j];
+    return QSV_OK;
+}
+
+qsv_status qsv_plan_pass_ops(qsv_plan p, size_t i, int* fused_idx)
+{
+    if (!p || !fused_idx) return fail(QSV_E_ARG, "null argument");
+    if (i >= p->hp.passes.size()) return fail(QSV_E_ARG, "pass index out of range");
+    const PassPlan& pp = p->hp.passes[i];
+    for (size_t j = 0; j < pp.ops.size(); ++j) fused_idx[j] = pp.ops[j];
+    return QSV_OK;
+}
+
+qsv_status qsv_plan_apply_range(qsv_state s, qsv_plan p, size_t first, size_t count)
+{
+    qsv_status st = check_state(s);
+    if (st != QSV_OK) return st;
+    if (!p) return fail(QSV_E_ARG, "null plan");
+    if (p->hp.n != s->n || p->hp.dtype != s->dtype) return fail(QSV_E_ARG, "plan does not match the state's n / dtype");
+    const size_t np = p->hp.passes.size();
+    if (first > np || count > np - first) return fail(QSV_E_ARG, "pass range out of bounds");
+    DeviceGuard g(s->device);
+    st = upload_plan(p, s->device);
+    if (st != QSV_OK) return st;
+    for (size_t i = first; i < first + count; ++i) {
+        const PassArgs& a = p->hp.pargs[i];
+        QSV_HIP(launch_pass(s->dtype, s->buf, a, p->hp.pgrid[i], p->d_ops, p->d_pool, p->d_ipool, s->stream));
+    }
+    return QSV_OK;
+}
+
+qsv_status qsv_plan_apply(qsv_state s, qsv_plan p)
+{
+    if (!p) return fail(QSV_E_ARG, "null plan");
+    return qsv_plan_apply_range(s, p, 0, p->hp.passes.size());
+}
+
+qsv_status qsv_apply_fused(qsv_state s, const qsv_gate* gates, size_t n_gates, const qsv_plan_opts* opts,
+                           qsv_plan_stats* stats)
+{
+    qsv_status st = check_state(s);
+    if (st != QSV_OK) return st;
+    qsv_plan p = nullptr;
+    st = qsv_plan_create(s->n, (qsv_dtype)s->dtype, gates, n_gates, opts, &p);
+    if (st != QSV_OK) return st;
+    if (stats) qsv_plan_get_stats(p, stats);
+    st = qsv_plan_apply(s, p);
+    {
+        DeviceGuard g(s->device);
+        const hipError_t e = hipStreamSynchronize(s->stream);
+        qsv_plan_free(p);
+        if (st == QSV_OK && e != hipSuccess) return fail(QSV_E_DEVICE, std::string("apply: ") + hipGetErrorString(e));
+    }
+    return st;
+}
+
+qsv_status qsv_norm(qsv_state s, double* out)
+{
+    qsv_status st = check_state(s);
+    if (st != QSV_OK) return st;
+    if (!out) return fail(QSV_E_ARG, "out is null");
+    DeviceGuard g(s->device);
+    const long long N = 1ll << s->n;
+    const int grid = norm_grid(N);
+    const size_t bytes = (size_t)grid * 2 * sizeof(double);
+    if ((st = ensure_work(s, bytes)) != QSV_OK) return st;
+    if ((st = ensure_hwork(s, bytes)) != QSV_OK) return st;
+    QSV_HIP(launch_norm(s->dtype, s->buf, N, s->d_work, grid, s->stream));
+    QSV_HIP(hipMemcpyAsync(s->h_work, s->d_work, bytes, hipMemcpyDeviceToHost, s->stream));
+    QSV_HIP(hipStreamSynchronize(s->stream));
+    NS acc;
+    for (int b = 0; b < grid; ++b) {
+        acc.add(s->h_work[2 * b]);
+        acc.c += s->h_work[2 * b + 1];
+    }
+    *out = acc.value();
+    return QSV_OK;
+}
+
+qsv_status qsv_expval_pauli(qsv_state s, const qsv_pauli_term* terms, size_t n_terms, double* per_term,
+                            double* sum)
+{
+    qsv_status st = check_state(s);
+    if (st != QSV_OK) return st;
+    if (n_terms && !terms) return fail(QSV_E_ARG, "terms is null");
+    std::vector<PTerm> pt;
+    std::string err;
+    if (!parse_terms(terms, n_terms, s->n, pt, err)) return fail(QSV_E_ARG, err);
+    DeviceGuard g(s->device);
+    std::vector<double> vals;
+    if ((st = expval_core(s, pt, vals)) != QSV_OK) return st;
+    NS acc;
+    for (size_t i = 0; i < n_terms; ++i) {
+        const double v = pt[i].coeff * vals[i];
+        if (per_term) per_term[i] = v;
+        acc.add(v);
+    }
+    if (sum) *sum = acc.value();
+    return QSV_OK;
+}
+
+qsv_status qsv_probs(qsv_state s, const int* qubits, int m, void* out, int out_on_device)
+{
+    qsv_status st = check_state(s);
+    if (st != QSV_OK) return st;
+    if (!out) return fail(QSV_E_ARG, "out is null");
+    const int n = s->n;
+    if (m < 1 || m > n) return fail(QSV_E_ARG, "m must be in [1, n]");
+    bool full = (m == n);
+    if (qubits) {
+        for (int j = 0; j < m; ++j) {
+            if (qubits[j] < 0 || qubits[j] >= n) return fail(QSV_E_ARG, "qubit out of range");
+            for (int i = 0; i < j; ++i)
+                if (qubits[i] == qubits[j]) return fail(QSV_E_ARG, "repeated qubit");
+            if (qubits[j] != j) full = false;
+        }
+    }
+    DeviceGuard g(s->device);
+    const long long N = 1ll << n;
+    if (full) {
+        const size_t bytes = (size_t)N * (s->dtype == QSV_C64 ? 4 : 8);
+        void* dst = out;
+        void* tmp = nullptr;
+        if (!out_on_device) {
+            if (hipMalloc(&tmp, bytes) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(QSV_E_OOM, "probability buffer allocation failed");
+            }
+            dst = tmp;
+        }
+        hipError_t e = launch_probs_full(s->dtype, s->buf, N, dst, s->stream);
+        if (e == hipSuccess && tmp) e = hipMemcpyAsync(out, tmp, bytes, hipMemcpyDeviceToHost, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (tmp) (void)hipFree(tmp);
+        if (e != hipSuccess) return fail(QSV_E_DEVICE, std::string("probs: ") + hipGetErrorString(e));
+        return QSV_OK;
+    }
+    MargArgs a{};
+    a.n = n;
+    a.m = m;
+    unsigned long long Q = 0;
+    for (int j = 0; j < m; ++j) {
+        a.q[j] = qubits ? qubits[j] : j;
+        Q |= 1ull << a.q[j];
+    }
+    int r = 0;
+    for (int b = 0; b < n; ++b)
+        if (!((Q >> b) & 1)) a.rest[r++] = b;
+    const long long M = 1ll << m, R = 1ll << (n - m);
+    long long nchunks = std::max<long long>(1, (1ll << 20) / M);
+    nchunks = std::min(nchunks, R);
+    a.nchunks = nchunks;
+    a.chunk = R / nchunks;
+    const size_t pbytes = (size_t)(M * nchunks) * 2 * sizeof(double);
+    const size_t obytes = (size_t)M * sizeof(double);
+    if ((st = ensure_work(s, pbytes + (out_on_device ? 0 : obytes))) != QSV_OK) return st;
+    double* partial = s->d_work;
+    double* dout = out_on_device ? (double*)out : (double*)((char*)s->d_work + pbytes);
+    QSV_HIP(launch_probs_marg(s->dtype, s->buf, a, partial, dout, s->stream));
+    if (!out_on_device) QSV_HIP(hipMemcpyAsync(out, dout, obytes, hipMemcpyDeviceToHost, s->stream));
+    QSV_HIP(hipStreamSynchronize(s->stream));
+    return QSV_OK;
+}
+
+// Adjoint-method gradient (Jones and Gacon's reverse sweep), for rotations
+// R_P(theta) = exp(-i theta P / 2) (Eq. 4):  dE/dtheta_l = Im <lambda_l| P_l |phi_l>, with
+// phi_l the state just after op l and lambda_l = U_{l+1}^dag ... U_L^dag H |psi>.
+// Consecutive rotations on distinct qubits commute, so every rotation of such a layer
+// is evaluated at the layer's end in one read pass over (lambda, phi); between
+// evaluation points phi and lambda are uncomputed with one fused plan of inverse gates.
+qsv_status qsv_adjoint_grad(int n, qsv_dtype dtype, const qsv_op* ops, size_t n_ops, const double* params, int B,
+                            int P, const qsv_pauli_term* H, size_t n_terms, double* energy, double* grad,
+                            void* stream)
+{
+    if (n < 1 || n > kMaxQubits) return fail(QSV_E_ARG, "n_qubits must be in [1, 34]");
+    if (dtype != QSV_C64 && dtype != QSV_C128) return fail(QSV_E_ARG, "bad dtype");
+    if (B < 0 || P < 0) return fail(QSV_E_ARG, "negative batch or parameter count");
+    if ((n_ops && !ops) || (B && P && !params) || (n_terms && !H) || (B && !energy) || (B && P && !grad))
+        return fail(QSV_E_ARG, "null argument");
+    // validate ops; fixed gates are read once
+    std::vector<InGate> fixed(n_ops);
+    std::string err;
+    for (size_t i = 0; i < n_ops; ++i) {
+        const qsv_op& o = ops[i];
+        if (o.kind == 0) {
+            qsv_gate g{};
+            g.k = o.k;
+            for (int j = 0; j < 5; ++j) g.targets[j] = o.targets[j];
+            g.diag = 0;
+            g.mat = o.mat;
+            if (!read_gate(g, n, fixed[i], err)) return fail(QSV_E_ARG, "op " + std::to_string(i) + ": " + err);
+        } else if (o.kind >= 1 && o.kind <= 3) {
+            if (o.targets[0] < 0 || o.targets[0] >= n) return fail(QSV_E_ARG, "rotation target out of range");
+            if (o.param < 0 || o.param >= P) return fail(QSV_E_ARG, "rotation parameter index out of range");
+        } else {
+            return fail(QSV_E_ARG, "op kind must be 0 (gate), 1 (RX), 2 (RY) or 3 (RZ)");
+        }
+    }
+    std::vector<PTerm> hterms;
+    if (!parse_terms(H, n_terms, n, hterms, err)) return fail(QSV_E_ARG, err);
+    if (B == 0) return QSV_OK;
+
+    // gate of op i under parameter vector th (inverse = conjugate transpose)
+    auto op_gate = [&](size_t i, const double* th, bool inverse) {
+        InGate g;
+        const qsv_op& o = ops[i];
+        if (o.kind == 0) {
+            g = fixed[i];
+        } else {
+            const double t = th[o.param];
+            const double c = std::cos(t / 2), sn = std::sin(t / 2);
+            const cd I(0, 1);
+            g.k = 1;
+            g.t[0] = o.targets[0];
+            for (int j = 1; j < kMaxK; ++j) g.t[j] = 0;
+            if (o.kind == 1) g.m = {c, -I * sn, -I * sn, c};
+            else if (o.kind == 2) g.m = {c, -sn, sn, c};
+            else g.m = {std::polar(1.0, -t / 2), 0, 0, std::polar(1.0, t / 2)};
+        }
+        if (inverse) {
+            const int d = 1 << g.k;
+            std::vector<cd> h((size_t)d * d);
+            for (int r = 0; r < d; ++r)
+                for (int c2 = 0; c2 < d; ++c2) h[(size_t)c2 * d + r] = std::conj(g.m[(size_t)r * d + c2]);
+            g.m = h;
+        }
+        return g;
+    };
+
+    qsv_state phi = nullptr, lam = nullptr;
+    qsv_status st = qsv_alloc(n, dtype, nullptr, 0, stream, &phi);
+    if (st != QSV_OK) return st;
+    st = qsv_alloc(n, dtype, nullptr, 0, stream, &lam);
+    if (st != QSV_OK) {
+        qsv_free(phi);
+        return st;
+    }
+    for (int b = 0; b < B && st == QSV_OK; ++b) {
+        const double* th = params + (size_t)b * P;
+        double* gb = grad + (size_t)b * P;
+        for (int j = 0; j < P; ++j) gb[j] = 0.0;
+        // forward: phi = U(theta)|0>
+        std::vector<InGate> fwd;
+        fwd.reserve(n_ops);
+        for (size_t i = 0; i < n_ops; ++i) fwd.push_back(op_gate(i, th, false));
+        if ((st = qsv_reset(phi)) != QSV_OK) break;
+        if ((st = apply_gates(phi, fwd)) != QSV_OK) break;
+        // energy and co-state lambda = H phi
+        std::vector<double> hv;
+        if ((st = expval_core(phi, hterms, hv)) != QSV_OK) break;
+        NS e;
+        for (size_t t = 0; t < hterms.size(); ++t) e.add(hterms[t].coeff * hv[t]);
+        energy[b] = e.value();
+        if ((st = pauli_sum_apply(lam, phi->buf, lam->buf, hterms)) != QSV_OK) break;
+        // reverse sweep
+        std::vector<InGate> pending;   // inverse gates still to apply, in application order
+        long long i = (long long)n_ops - 1;
+        while (i >= 0 && st == QSV_OK) {
+            if (ops[i].kind == 0) {
+                pending.push_back(op_gate((size_t)i, th, true));
+                --i;
+                continue;
+            }
+            // a layer: consecutive rotations (walking backwards) on distinct qubits
+            unsigned long long used = 0;
+            long long j = i;
+            std::vector<long long> layer;
+            while (j >= 0 && ops[j].kind != 0 && !((used >> ops[j].targets[0]) & 1)) {
+                used |= 1ull << ops[j].targets[0];
+                layer.push_back(j);
+                --j;
+            }
+            if (!pending.empty()) {
+                if ((st = apply_gates(phi, pending)) != QSV_OK) break;
+                if ((st = apply_gates(lam, pending)) != QSV_OK) break;
+                pending.clear();
+            }
+            std::vector<PTerm> gterms(layer.size());
+            for (size_t l = 0; l < layer.size(); ++l) {
+                const qsv_op& o = ops[layer[l]];
+                const unsigned long long bit = 1ull << o.targets[0];
+                PTerm t;
+                if (o.kind == 1) t.x = bit;                               // X
+                else if (o.kind == 2) { t.x = bit; t.z = bit; t.ny = 1; }  // Y
+                else t.z = bit;                                            // Z
+                t.coeff = 1.0;
+                gterms[l] = t;
+            }
+            std::vector<double> gv;
+            if ((st = pauli_elements(lam, lam->buf, phi->buf, gterms, true, gv)) != QSV_OK) break;
+            for (size_t l = 0; l < layer.size(); ++l) {
+                gb[ops[layer[l]].param] += gv[l];
+                pending.push_back(op_gate((size_t)layer[l], th, true));
+            }
+            i = j;
+        }
+    }
+    qsv_free(phi);
+    qsv_free(lam);
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,575 @@
+// kernels.hip -- HIP kernels of libqsv for gfx950 (MI355X, CDNA4, wave64).
+//
+// State layout: 2^n interleaved complex numbers (float2 for complex64, double2 for
+// complex128), qubit t = bit t of the index (Eq. 2 / Eq. 3).
+//
+// Apply pass (k_pass): one workgroup per tile.  A tile is 2^m amplitudes whose
+// indices differ only in the pass's m tile qubits: the L lowest qubits (so each tile
+// row is a contiguous run of 2^L amplitudes in HBM) plus m - L higher qubits (rows
+// strided by 2^q).  The workgroup streams its tile from HBM into LDS, applies every
+// op of the pass in order on the LDS copy (dense k-qubit unitaries, diagonal phase
+// tables, generalised permutations), and streams it back: one HBM round trip per
+// pass however many fused gates it carries.  When the whole state fits in LDS the
+// single tile is the state and one launch runs the whole circuit.
+//
+// Reductions read the state once, accumulate in FP64 per thread (products of FP32
+// operands are exact in FP64), reduce each workgroup in a fixed order, and leave
+// one partial per workgroup; the host combines partials in a fixed order with
+// Neumaier's compensated sum, so results are run-to-run deterministic.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "qsv_internal.h"
+
+namespace qsv {
+
+template <typename R> struct CT;
+template <> struct CT<float> { using T = float2; };
+template <> struct CT<double> { using T = double2; };
+
+template <typename C>
+__device__ __forceinline__ C cmul(C a, C b)
+{
+    C r;
+    r.x = a.x * b.x - a.y * b.y;
+    r.y = a.x * b.y + a.y * b.x;
+    return r;
+}
+
+template <typename C>
+__device__ __forceinline__ void cmac(C& acc, C a, C b)
+{
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(a.y, b.x, acc.y);
+}
+
+__device__ __forceinline__ long long tile_base(const PassArgs& a, long long t)
+{
+    long long base = 0;
+    for (int i = 0; i < a.nruns; ++i) {
+        base |= (t & ((1ll << a.run_len[i]) - 1)) << a.run_pos[i];
+        t >>= a.run_len[i];
+    }
+    return base;
+}
+
+// Offset (relative to the tile base) of the local bits [lo, hi) of local index e.
+__device__ __forceinline__ long long local_off_bits(const PassArgs& a, int e, int lo, int hi)
+{
+    long long o = 0;
+    for (int i = lo; i < hi; ++i) {
+        if ((e >> i) & 1) o += (i < a.L) ? (1ll << i) : a.hstride[i - a.L];
+    }
+    return o;
+}
+
+// Move a tile between HBM and LDS.  Local index e = e0 + tid: the bits below 8 come
+// from the thread id (offset computed once), the bits above from the uniform loop
+// counter (offset computed in scalar registers).
+template <typename C, bool LOAD>
+__device__ __forceinline__ void move_tile(C* __restrict__ st, C* __restrict__ lds, const PassArgs& a,
+                                          long long base)
+{
+    const int T = 1 << a.m;
+    const int tid = threadIdx.x;
+    const int lowb = a.m < kLogThreads ? a.m : kLogThreads;
+    const long long toff = base + local_off_bits(a, tid, 0, lowb);
+    for (int e0 = 0; e0 < T; e0 += kThreads) {
+        const long long soff = local_off_bits(a, e0, kLogThreads, a.m);
+        const int e = e0 + tid;
+        if (e < T) {
+            if (LOAD) lds[e] = st[toff + soff];
+            else st[toff + soff] = lds[e];
+        }
+    }
+}
+
+// Offset of local basis row r of an op inside the tile: bit j of r sits at lpos[j].
+template <int K>
+__device__ __forceinline__ int row_off(int r, const DevOp& op)
+{
+    int o = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+        if ((r >> j) & 1) o += 1 << op.lpos[j];
+    return o;
+}
+
+// Group g of an op: insert a zero bit at each target position (ascending).
+template <int K>
+__device__ __forceinline__ int group_base(int g, const DevOp& op)
+{
+    int b = g;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const int p = op.lpos[j];
+        b = ((b >> p) << (p + 1)) | (b & ((1 << p) - 1));
+    }
+    return b;
+}
+
+template <typename C, int K>
+__device__ void op_dense(C* __restrict__ lds, int T, const DevOp& op, const C* __restrict__ M)
+{
+    constexpr int D = 1 << K;
+    const int G = T >> K;
+    for (int g = threadIdx.x; g < G; g += kThreads) {
+        const int b = group_base<K>(g, op);
+        C v[D];
+#pragma unroll
+        for (int r = 0; r < D; ++r) v[r] = lds[b + row_off<K>(r, op)];
+        // rows are not unrolled for wide gates: the row's matrix entries are uniform
+        // (scalar) loads, the inputs stay in registers
+        constexpr int RU = K <= 3 ? D : 1;
+#pragma unroll RU
+        for (int r = 0; r < D; ++r) {
+            C acc;
+            acc.x = 0;
+            acc.y = 0;
+#pragma unroll
+            for (int c = 0; c < D; ++c) cmac(acc, M[r * D + c], v[c]);
+            lds[b + row_off<K>(r, op)] = acc;
+        }
+    }
+}
+
+template <typename C, int K>
+__device__ void op_perm(C* __restrict__ lds, int T, const DevOp& op, const C* __restrict__ ph,
+                        const int* __restrict__ src)
+{
+    constexpr int D = 1 << K;
+    const int G = T >> K;
+    const bool phased = op.flags != 0;
+    for (int g = threadIdx.x; g < G; g += kThreads) {
+        const int b = group_base<K>(g, op);
+        C v[D];
+#pragma unroll
+        for (int r = 0; r < D; ++r) v[r] = lds[b + row_off<K>(src[r], op)];
+#pragma unroll
+        for (int r = 0; r < D; ++r) lds[b + row_off<K>(r, op)] = phased ? cmul(ph[r], v[r]) : v[r];
+    }
+}
+
+template <typename C>
+__device__ void op_diag(C* __restrict__ lds, int T, const DevOp& op, const C* __restrict__ Dg,
+                        long long base)
+{
+    // targets outside the tile contribute a per-tile constant part of the table index
+    int gfix = 0, lp[kMaxDiagK];
+#pragma unroll
+    for (int j = 0; j < kMaxDiagK; ++j) {
+        lp[j] = (j < op.k) ? op.lpos[j] : -1;
+        if (j < op.k && lp[j] < 0) gfix |= (int)((base >> op.gbit[j]) & 1) << j;
+    }
+    for (int e = threadIdx.x; e < T; e += kThreads) {
+        int idx = gfix;
+#pragma unroll
+        for (int j = 0; j < kMaxDiagK; ++j)
+            if (lp[j] >= 0) idx |= ((e >> lp[j]) & 1) << j;
+        lds[e] = cmul(lds[e], Dg[idx]);
+    }
+}
+
+template <typename C>
+__device__ void apply_ops(C* __restrict__ lds, int T, const DevOp* __restrict__ ops, int op_begin,
+                          int op_count, const C* __restrict__ pool, const int* __restrict__ ipool,
+                          long long base)
+{
+    for (int oi = 0; oi < op_count; ++oi) {
+        const DevOp op = ops[op_begin + oi];
+        const C* M = pool + op.off;
+        if (op.kind == OP_DENSE) {
+            switch (op.k) {
+            case 1: op_dense<C, 1>(lds, T, op, M); break;
+            case 2: op_dense<C, 2>(lds, T, op, M); break;
+            case 3: op_dense<C, 3>(lds, T, op, M); break;
+            case 4: op_dense<C, 4>(lds, T, op, M); break;
+            default: op_dense<C, 5>(lds, T, op, M); break;
+            }
+        } else if (op.kind == OP_PERM) {
+            const int* S = ipool + op.ioff;
+            switch (op.k) {
+            case 1: op_perm<C, 1>(lds, T, op, M, S); break;
+            case 2: op_perm<C, 2>(lds, T, op, M, S); break;
+            case 3: op_perm<C, 3>(lds, T, op, M, S); break;
+            case 4: op_perm<C, 4>(lds, T, op, M, S); break;
+            default: op_perm<C, 5>(lds, T, op, M, S); break;
+            }
+        } else {
+            op_diag<C>(lds, T, op, M, base);
+        }
+        __syncthreads();
+    }
+}
+
+template <typename C>
+__global__ __launch_bounds__(kThreads) void k_pass(C* __restrict__ st, const PassArgs a,
+                                                   const DevOp* __restrict__ ops,
+                                                   const C* __restrict__ pool,
+                                                   const int* __restrict__ ipool)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    C* lds = reinterpret_cast<C*>(smem);
+    const long long base = tile_base(a, blockIdx.x);
+    move_tile<C, true>(st, lds, a, base);
+    __syncthreads();
+    apply_ops<C>(lds, 1 << a.m, ops, a.op_begin, a.op_count, pool, ipool, base);
+    move_tile<C, false>(st, lds, a, base);
+}
+
+template <typename C>
+__global__ __launch_bounds__(kThreads) void k_zero(C* __restrict__ st, long long N)
+{
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
+        C z;
+        z.x = 0;
+        z.y = 0;
+        st[i] = z;
+    }
+}
+
+template <typename C>
+__global__ __launch_bounds__(kThreads) void k_init_zero(C* __restrict__ st, long long N)
+{
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
+        C z;
+        z.x = (i == 0) ? 1 : 0;
+        z.y = 0;
+        st[i] = z;
+    }
+}
+
+// ------------------------------------------------------------------ reductions
+
+struct NSum {
+    double s, c;
+};
+
+__device__ __forceinline__ void nadd(NSum& a, double x)
+{
+    const double t = a.s + x;
+    a.c += (fabs(a.s) >= fabs(x)) ? ((a.s - t) + x) : ((x - t) + a.s);
+    a.s = t;
+}
+
+__device__ __forceinline__ NSum ncombine(NSum a, NSum b)
+{
+    NSum r = a;
+    nadd(r, b.s);
+    r.c += b.c;
+    return r;
+}
+
+// Fixed-order workgroup reduction of Neumaier pairs: butterfly within each wave,
+// then wave results combined in wave order by thread 0.  Returns the result in
+// thread 0.
+__device__ NSum block_reduce(NSum v, NSum* scratch)
+{
+    for (int d = 32; d >= 1; d >>= 1) {
+        NSum o;
+        o.s = __shfl_xor(v.s, d);
+        o.c = __shfl_xor(v.c, d);
+        v = ((threadIdx.x & d) == 0) ? ncombine(v, o) : ncombine(o, v);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) scratch[w] = v;
+    __syncthreads();
+    NSum r = {0.0, 0.0};
+    if (threadIdx.x == 0) {
+        r = scratch[0];
+        for (int i = 1; i < (int)(blockDim.x >> 6); ++i) r = ncombine(r, scratch[i]);
+    }
+    __syncthreads();
+    return r;
+}
+
+template <typename C>
+__global__ __launch_bounds__(kThreads) void k_norm(const C* __restrict__ st, long long N,
+                                                   double* __restrict__ partial)
+{
+    __shared__ NSum scratch[kThreads / 64];
+    NSum a = {0.0, 0.0};
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
+        const C v = st[i];
+        const double x = v.x, y = v.y;
+        nadd(a, x * x + y * y);
+    }
+    const NSum r = block_reduce(a, scratch);
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = r.s;
+        partial[2 * blockIdx.x + 1] = r.c;
+    }
+}
+
+// Pauli matrix elements over tiles: value_t = sum_k Re( i^ny conj(a[k xor x]) b[k] ) *
+// (-1)^popcount(k & zy), i.e. Re <a|P_t|b> (ny may carry an extra 3 to give Im instead).
+// Each term's X/Y support lies inside the tile, so the partner a[k xor x] is read from
+// the LDS copy of a's tile; b is a itself (expectation values) or a second state read
+// straight from HBM at the same addresses (adjoint gradients).
+template <typename C, bool TWO>
+__global__ __launch_bounds__(kThreads) void k_expval(const C* __restrict__ sa, const C* __restrict__ sb,
+                                                     const PassArgs a, const TermArgs t, long long ntiles,
+                                                     double* __restrict__ partial)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    C* lds = reinterpret_cast<C*>(smem);
+    __shared__ NSum scratch[kThreads / 64];
+    const int T = 1 << a.m;
+    const int tid = threadIdx.x;
+    const int lowb = a.m < kLogThreads ? a.m : kLogThreads;
+    const long long tlocal = local_off_bits(a, tid, 0, lowb);
+    double acc[kMaxTermsPerLaunch];
+#pragma unroll
+    for (int i = 0; i < kMaxTermsPerLaunch; ++i) acc[i] = 0.0;
+    for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const long long base = tile_base(a, tile);
+        move_tile<C, true>(const_cast<C*>(sa), lds, a, base);
+        __syncthreads();
+        int gpar[kMaxTermsPerLaunch];
+#pragma unroll
+        for (int i = 0; i < kMaxTermsPerLaunch; ++i)
+            gpar[i] = (i < t.nterms) ? (__popcll(base & t.zglob[i]) & 1) : 0;
+        for (int e0 = 0; e0 < T; e0 += kThreads) {
+            const int e = e0 + tid;
+            if (e >= T) break;
+            C be;
+            if (TWO) be = sb[base + tlocal + local_off_bits(a, e0, kLogThreads, a.m)];
+            else be = lds[e];
+#pragma unroll
+            for (int i = 0; i < kMaxTermsPerLaunch; ++i) {
+                if (i < t.nterms) {
+                    const C ap = lds[e ^ t.xloc[i]];
+                    const double re = (double)ap.x * (double)be.x + (double)ap.y * (double)be.y;
+                    const double im = (double)ap.x * (double)be.y - (double)ap.y * (double)be.x;
+                    const int q = t.ny[i] & 3;
+                    double val = (q == 0) ? re : (q == 1) ? -im : (q == 2) ? -re : im;
+                    const int par = (__popc(e & t.zloc[i]) + gpar[i]) & 1;
+                    acc[i] += par ? -val : val;
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < kMaxTermsPerLaunch; ++i) {
+        if (i < t.nterms) {
+            NSum v = {acc[i], 0.0};
+            const NSum r = block_reduce(v, scratch);
+            if (threadIdx.x == 0) {
+                partial[((long long)blockIdx.x * t.nterms + i) * 2] = r.s;
+                partial[((long long)blockIdx.x * t.nterms + i) * 2 + 1] = r.c;
+            }
+        }
+    }
+}
+
+// out = sum_t coeff_t P_t in (accumulate != 0: out += ...), with
+// (P in)[k] = i^ny (-1)^popcount((k xor x) & zy) in[k xor x].  Each thread gathers its
+// amplitude's partners straight from HBM / L2.
+template <typename C>
+__global__ __launch_bounds__(kThreads) void k_pauli_apply(const C* __restrict__ in, C* __restrict__ out,
+                                                          long long N, const PauliSumArgs p, int accumulate)
+{
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < N; k += stride) {
+        double re = 0.0, im = 0.0;
+        if (accumulate) {
+            const C o = out[k];
+            re = o.x;
+            im = o.y;
+        }
+        for (int i = 0; i < p.nterms; ++i) {
+            const long long j = k ^ p.x[i];
+            const C v = in[j];
+            double vr = v.x, vi = v.y;
+            const int q = p.ny[i] & 3;   // multiply by i^q
+            double tr = (q == 0) ? vr : (q == 1) ? -vi : (q == 2) ? -vr : vi;
+            double ti = (q == 0) ? vi : (q == 1) ? vr : (q == 2) ? -vi : -vr;
+            const double c = (__popcll(j & p.z[i]) & 1) ? -p.coeff[i] : p.coeff[i];
+            re = fma(c, tr, re);
+            im = fma(c, ti, im);
+        }
+        C o;
+        o.x = re;
+        o.y = im;
+        out[k] = o;
+    }
+}
+
+template <typename C, typename R>
+__global__ __launch_bounds__(kThreads) void k_probs_full(const C* __restrict__ st, long long N,
+                                                         R* __restrict__ out)
+{
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
+        const C v = st[i];
+        out[i] = v.x * v.x + v.y * v.y;
+    }
+}
+
+template <typename C>
+__global__ __launch_bounds__(kThreads) void k_probs_marg(const C* __restrict__ st, const MargArgs a,
+                                                         double* __restrict__ partial)
+{
+    const long long M = 1ll << a.m;
+    const long long total = M * a.nchunks;
+    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= total) return;
+    const long long o = gid % M;
+    const long long ch = gid / M;
+    long long ob = 0;
+    for (int j = 0; j < a.m; ++j) ob |= ((o >> j) & 1) << a.q[j];
+    const int nr = a.n - a.m;
+    NSum s = {0.0, 0.0};
+    for (long long r = ch * a.chunk; r < (ch + 1) * a.chunk; ++r) {
+        long long idx = ob;
+        for (int j = 0; j < nr; ++j) idx |= ((r >> j) & 1) << a.rest[j];
+        const C v = st[idx];
+        const double x = v.x, y = v.y;
+        nadd(s, x * x + y * y);
+    }
+    partial[2 * (ch * M + o)] = s.s;
+    partial[2 * (ch * M + o) + 1] = s.c;
+}
+
+// out[o] = Neumaier sum over chunks of partial[(chunk*M + o)] (pairs), fixed order.
+__global__ __launch_bounds__(kThreads) void k_sum_chunks(const double* __restrict__ partial, long long M,
+                                                         long long nchunks, double* __restrict__ out)
+{
+    const long long o = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= M) return;
+    NSum s = {0.0, 0.0};
+    for (long long c = 0; c < nchunks; ++c) {
+        nadd(s, partial[2 * (c * M + o)]);
+        s.c += partial[2 * (c * M + o) + 1];
+    }
+    out[o] = s.s + s.c;
+}
+
+// ------------------------------------------------------------------ launchers
+
+template <typename R>
+hipError_t launch_pass_t(void* st, const PassArgs& a, long long grid, const DevOp* ops, const void* pool,
+                         const int* ipool, hipStream_t s)
+{
+    using C = typename CT<R>::T;
+    const size_t lds = sizeof(C) << a.m;
+    static bool attr_set = false;   // allow the full 64 KiB tile of dynamic LDS
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_pass<C>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_pass<C>, dim3((unsigned)grid), dim3(kThreads), lds, s, (C*)st, a, ops,
+                       (const C*)pool, ipool);
+    return hipGetLastError();
+}
+
+hipError_t launch_pass(int dtype, void* st, const PassArgs& a, long long grid, const DevOp* ops,
+                       const void* pool, const int* ipool, hipStream_t s)
+{
+    return dtype == 0 ? launch_pass_t<float>(st, a, grid, ops, pool, ipool, s)
+                      : launch_pass_t<double>(st, a, grid, ops, pool, ipool, s);
+}
+
+hipError_t launch_init_zero(int dtype, void* st, long long N, hipStream_t s)
+{
+    const long long blocks = std::min<long long>((N + kThreads - 1) / kThreads, 8192);
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_init_zero<float2>, dim3((unsigned)blocks), dim3(kThreads), 0, s, (float2*)st, N);
+    else
+        hipLaunchKernelGGL(k_init_zero<double2>, dim3((unsigned)blocks), dim3(kThreads), 0, s, (double2*)st, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(int dtype, void* st, long long N, hipStream_t s)
+{
+    const long long blocks = std::min<long long>((N + kThreads - 1) / kThreads, 8192);
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_zero<float2>, dim3((unsigned)blocks), dim3(kThreads), 0, s, (float2*)st, N);
+    else
+        hipLaunchKernelGGL(k_zero<double2>, dim3((unsigned)blocks), dim3(kThreads), 0, s, (double2*)st, N);
+    return hipGetLastError();
+}
+
+int norm_grid(long long N)
+{
+    return (int)std::min<long long>(1024, std::max<long long>(1, N / kThreads));
+}
+
+hipError_t launch_norm(int dtype, const void* st, long long N, double* partial, int grid, hipStream_t s)
+{
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_norm<float2>, dim3(grid), dim3(kThreads), 0, s, (const float2*)st, N, partial);
+    else
+        hipLaunchKernelGGL(k_norm<double2>, dim3(grid), dim3(kThreads), 0, s, (const double2*)st, N, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_expval(int dtype, const void* sa, const void* sb, const PassArgs& a, const TermArgs& t,
+                         long long ntiles, int grid, double* partial, hipStream_t s)
+{
+    const bool two = sb != nullptr && sb != sa;
+    if (dtype == 0) {
+        auto k = two ? k_expval<float2, true> : k_expval<float2, false>;
+        hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), sizeof(float2) << a.m, s, (const float2*)sa,
+                           (const float2*)sb, a, t, ntiles, partial);
+    } else {
+        auto k = two ? k_expval<double2, true> : k_expval<double2, false>;
+        hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), sizeof(double2) << a.m, s, (const double2*)sa,
+                           (const double2*)sb, a, t, ntiles, partial);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pauli_apply(int dtype, const void* in, void* out, long long N, const PauliSumArgs& p,
+                              int accumulate, hipStream_t s)
+{
+    const long long blocks = std::min<long long>((N + kThreads - 1) / kThreads, 16384);
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_pauli_apply<float2>, dim3((unsigned)blocks), dim3(kThreads), 0, s, (const float2*)in,
+                           (float2*)out, N, p, accumulate);
+    else
+        hipLaunchKernelGGL(k_pauli_apply<double2>, dim3((unsigned)blocks), dim3(kThreads), 0, s,
+                           (const double2*)in, (double2*)out, N, p, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_probs_full(int dtype, const void* st, long long N, void* out, hipStream_t s)
+{
+    const long long blocks = std::min<long long>((N + kThreads - 1) / kThreads, 8192);
+    if (dtype == 0)
+        hipLaunchKernelGGL((k_probs_full<float2, float>), dim3((unsigned)blocks), dim3(kThreads), 0, s,
+                           (const float2*)st, N, (float*)out);
+    else
+        hipLaunchKernelGGL((k_probs_full<double2, double>), dim3((unsigned)blocks), dim3(kThreads), 0, s,
+                           (const double2*)st, N, (double*)out);
+    return hipGetLastError();
+}
+
+hipError_t launch_probs_marg(int dtype, const void* st, const MargArgs& a, double* partial, double* out,
+                             hipStream_t s)
+{
+    const long long M = 1ll << a.m;
+    const long long total = M * a.nchunks;
+    const long long blocks = (total + kThreads - 1) / kThreads;
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_probs_marg<float2>, dim3((unsigned)blocks), dim3(kThreads), 0, s,
+                           (const float2*)st, a, partial);
+    else
+        hipLaunchKernelGGL(k_probs_marg<double2>, dim3((unsigned)blocks), dim3(kThreads), 0, s,
+                           (const double2*)st, a, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sum_chunks, dim3((unsigned)((M + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
+                       (const double*)partial, M, a.nchunks, out);
+    return hipGetLastError();
+}
+
+}  // namespace qsv

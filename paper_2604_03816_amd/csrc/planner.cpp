@@ -1,0 +1,493 @@
+// planner.cpp -- DAG gate fusion (Section 5.2, Algorithm 2) and HBM pass scheduling.
+//
+// DAG (Section 5.1): one scan keeps, per qubit, the most recent gate; the edges are
+// these immediate per-qubit predecessors, so |E| <= sum |q(v)| (Eq. 8).  Here the DAG
+// is stored as a doubly linked list of nodes per qubit ("line"): prev/next of a node
+// on each of its qubits.
+//
+// Fusion (Algorithm 2): repeated sweeps in topological order; for each gate v and each
+// predecessor u, merge v into u when
+//   (1) u is a predecessor of v,
+//   (2) |q(u) U q(v)| <= kmax  (q_max^fuse),
+//   (3) u is v's predecessor on every shared qubit,
+//   (4) the merge keeps the graph acyclic.  The paper's conditions (1)-(3) alone allow
+//       merges that skip an intervening gate (u{0,1}, w{1,2}, v{0,2}: u and v share
+//       qubit 0 with nothing between them there, yet w must run between them).  A merge
+//       is sound iff no other path u ~> v exists; we accept it when every other
+//       predecessor of v precedes u in the sweep's topological order (then none is a
+//       descendant of u), or every other successor of u follows v (then no path from u
+//       through them reaches v).  Either rule also gives the fused node a valid slot in
+//       the order, so one order serves the whole sweep.
+//   (5) cost-aware mode only: the fused op costs no more arithmetic than its parts
+//       plus the per-op overhead it removes -- the trade-off of Eq. 13, where fused
+//       gates have a higher per-gate cost c_2 than unfused ones (c_1).
+// The fused matrix is U_v . U_u on the union of the targets (Eq. 9), each factor
+// embedded as identity on the qubits it does not act on; products in FP64.
+//
+// Pass scheduling: the fused gates, in topological order, are grouped greedily into
+// HBM passes.  A pass holds a tile of 2^m amplitudes on chip: the L lowest qubits
+// (contiguous in memory, so every tile row is a coalesced run) plus up to m - L other
+// qubits.  A gate joins the current pass when its targets fit in the tile, none of
+// its qubits is blocked by an earlier deferred gate, and the pass's arithmetic budget
+// allows.  Diagonal gates need no tile capacity: qubits outside the tile are
+// constant within a tile, so their phase is a per-tile constant.
+#include "planner.h"
+
+#include <algorithm>
+#include <cmath>
+#include <queue>
+
+namespace qsv {
+
+PlanOpts default_opts(int dtype)
+{
+    PlanOpts o;
+    if (dtype == 0) {   // complex64: 8-byte amplitudes
+        o.tile_qubits = 12;
+        o.low_qubits = 5;
+        o.whole_state_max = 13;
+        o.pass_budget = 112;
+        o.sigma = 8;
+    } else {            // complex128: 16-byte amplitudes
+        o.tile_qubits = 12;
+        o.low_qubits = 4;
+        o.whole_state_max = 12;
+        o.pass_budget = 224;
+        o.sigma = 8;
+    }
+    return o;
+}
+
+int classify(const std::vector<cd>& m, int k)
+{
+    const int d = 1 << k;
+    bool diag = true;
+    for (int r = 0; r < d && diag; ++r)
+        for (int c = 0; c < d; ++c)
+            if (r != c && m[(size_t)r * d + c] != cd(0, 0)) { diag = false; break; }
+    if (diag) return OP_DIAG;
+    std::vector<int> colcount(d, 0);
+    for (int r = 0; r < d; ++r) {
+        int cnt = 0;
+        for (int c = 0; c < d; ++c)
+            if (m[(size_t)r * d + c] != cd(0, 0)) { ++cnt; ++colcount[c]; }
+        if (cnt != 1) return OP_DENSE;
+    }
+    for (int c = 0; c < d; ++c)
+        if (colcount[c] != 1) return OP_DENSE;
+    return OP_PERM;
+}
+
+double op_fma(const FGate& g)
+{
+    const int d = 1 << g.k;
+    if (g.kind == OP_DENSE) return 4.0 * d;     // 2^k complex MACs per amplitude
+    if (g.kind == OP_DIAG) return 4.0;          // one complex multiply
+    for (int r = 0; r < d; ++r) {               // permutation: free unless it has phases
+        for (int c = 0; c < d; ++c) {
+            const cd v = g.m[(size_t)r * d + c];
+            if (v != cd(0, 0) && v != cd(1, 0)) return 4.0;
+        }
+    }
+    return 0.0;
+}
+
+namespace {
+
+bool is_identity(const FGate& g)
+{
+    const int d = 1 << g.k;
+    for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c)
+            if (g.m[(size_t)r * d + c] != (r == c ? cd(1, 0) : cd(0, 0))) return false;
+    return true;
+}
+
+// Embed matrix `a` (local bit j <-> qa[j], ascending, ka bits) into the ascending qubit
+// list Q (kq bits): E[r', r] = a[sub(r'), sub(r)] when r' and r agree outside qa, else 0.
+std::vector<cd> embed(const std::vector<cd>& a, const int* qa, int ka, const int* Q, int kq)
+{
+    const int dq = 1 << kq;
+    int pos[kMaxK];
+    int amask = 0;
+    for (int j = 0; j < ka; ++j) {
+        int p = 0;
+        while (Q[p] != qa[j]) ++p;
+        pos[j] = p;
+        amask |= 1 << p;
+    }
+    auto sub = [&](int r) {
+        int s = 0;
+        for (int j = 0; j < ka; ++j) s |= ((r >> pos[j]) & 1) << j;
+        return s;
+    };
+    const int da = 1 << ka;
+    std::vector<cd> e((size_t)dq * dq, cd(0, 0));
+    for (int r = 0; r < dq; ++r)
+        for (int c = 0; c < dq; ++c)
+            if ((r & ~amask) == (c & ~amask)) e[(size_t)r * dq + c] = a[(size_t)sub(r) * da + sub(c)];
+    return e;
+}
+
+std::vector<cd> matmul(const std::vector<cd>& A, const std::vector<cd>& B, int d)
+{
+    std::vector<cd> C((size_t)d * d, cd(0, 0));
+    for (int i = 0; i < d; ++i)
+        for (int l = 0; l < d; ++l) {
+            const cd a = A[(size_t)i * d + l];
+            if (a == cd(0, 0)) continue;
+            for (int j = 0; j < d; ++j) C[(size_t)i * d + j] += a * B[(size_t)l * d + j];
+        }
+    return C;
+}
+
+// Canonical form of an input gate: ascending targets, rows/columns permuted to match.
+FGate canonical(const InGate& g, int index)
+{
+    FGate f;
+    f.k = g.k;
+    int order[kMaxK];
+    for (int j = 0; j < g.k; ++j) order[j] = j;
+    std::sort(order, order + g.k, [&](int a, int b) { return g.t[a] < g.t[b]; });
+    for (int j = 0; j < g.k; ++j) f.q[j] = g.t[order[j]];
+    const int d = 1 << g.k;
+    auto remap = [&](int r) {  // new local index -> old local index
+        int o = 0;
+        for (int j = 0; j < g.k; ++j) o |= ((r >> j) & 1) << order[j];
+        return o;
+    };
+    f.m.assign((size_t)d * d, cd(0, 0));
+    for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c) f.m[(size_t)r * d + c] = g.m[(size_t)remap(r) * d + remap(c)];
+    f.kind = classify(f.m, f.k);
+    f.first = index;
+    return f;
+}
+
+struct Node {
+    FGate g;
+    bool alive = true;
+    int prev[kMaxK];  // per target slot: node index of the predecessor on that qubit, -1 if none
+    int next[kMaxK];
+};
+
+int slot_of(const Node& nd, int qubit)
+{
+    for (int j = 0; j < nd.g.k; ++j)
+        if (nd.g.q[j] == qubit) return j;
+    return -1;
+}
+
+// Kahn's algorithm; ties broken by the smallest member circuit index (deterministic).
+std::vector<int> topo_order(const std::vector<Node>& nodes)
+{
+    const int N = (int)nodes.size();
+    std::vector<int> indeg(N, 0);
+    for (int i = 0; i < N; ++i) {
+        if (!nodes[i].alive) continue;
+        int seen[kMaxK], ns = 0;
+        for (int j = 0; j < nodes[i].g.k; ++j) {
+            const int p = nodes[i].prev[j];
+            if (p < 0) continue;
+            bool dup = false;
+            for (int s = 0; s < ns; ++s) dup |= seen[s] == p;
+            if (!dup) seen[ns++] = p;
+        }
+        indeg[i] = ns;
+    }
+    using Item = std::pair<int, int>;  // (first, node)
+    std::priority_queue<Item, std::vector<Item>, std::greater<Item>> ready;
+    for (int i = 0; i < N; ++i)
+        if (nodes[i].alive && indeg[i] == 0) ready.push({nodes[i].g.first, i});
+    std::vector<int> order;
+    order.reserve(N);
+    while (!ready.empty()) {
+        const int u = ready.top().second;
+        ready.pop();
+        order.push_back(u);
+        int seen[kMaxK], ns = 0;
+        for (int j = 0; j < nodes[u].g.k; ++j) {
+            const int s = nodes[u].next[j];
+            if (s < 0) continue;
+            bool dup = false;
+            for (int t = 0; t < ns; ++t) dup |= seen[t] == s;
+            if (dup) continue;
+            seen[ns++] = s;
+            if (--indeg[s] == 0) ready.push({nodes[s].g.first, s});
+        }
+    }
+    return order;
+}
+
+FGate fuse_pair(const FGate& u, const FGate& v, int kmax, bool& ok)
+{
+    int Q[2 * kMaxK], kq = 0;
+    for (int j = 0; j < u.k; ++j) Q[kq++] = u.q[j];
+    for (int j = 0; j < v.k; ++j) {
+        bool dup = false;
+        for (int i = 0; i < u.k; ++i) dup |= u.q[i] == v.q[j];
+        if (!dup) Q[kq++] = v.q[j];
+    }
+    ok = kq <= kmax;
+    FGate f;
+    if (!ok) return f;
+    std::sort(Q, Q + kq);
+    f.k = kq;
+    for (int j = 0; j < kq; ++j) f.q[j] = Q[j];
+    const int d = 1 << kq;
+    const std::vector<cd> eu = embed(u.m, u.q, u.k, Q, kq);
+    const std::vector<cd> ev = embed(v.m, v.q, v.k, Q, kq);
+    f.m = matmul(ev, eu, d);  // Eq. 9: U_fused = U_v . U_u (u applied first)
+    f.kind = classify(f.m, kq);
+    f.first = std::min(u.first, v.first);
+    f.members = u.members + v.members;
+    return f;
+}
+
+void run_fusion(std::vector<Node>& nodes, const PlanOpts& o)
+{
+    const int N = (int)nodes.size();
+    std::vector<int> pos(N, 0);
+    bool changed = true;
+    while (changed) {
+        changed = false;
+        const std::vector<int> order = topo_order(nodes);
+        for (int i = 0; i < (int)order.size(); ++i) pos[order[i]] = i;
+        for (const int v : order) {
+            if (!nodes[v].alive) continue;
+            // distinct predecessors of v, nearest (latest in the order) first
+            int preds[kMaxK], np = 0;
+            for (int j = 0; j < nodes[v].g.k; ++j) {
+                const int p = nodes[v].prev[j];
+                if (p < 0) continue;
+                bool dup = false;
+                for (int s = 0; s < np; ++s) dup |= preds[s] == p;
+                if (!dup) preds[np++] = p;
+            }
+            std::sort(preds, preds + np, [&](int a, int b) { return pos[a] > pos[b]; });
+            for (int pi = 0; pi < np; ++pi) {
+                const int u = preds[pi];
+                Node& U = nodes[u];
+                Node& V = nodes[v];
+                // (3) u is v's predecessor on every shared qubit
+                bool sole = true;
+                for (int j = 0; j < V.g.k && sole; ++j)
+                    if (slot_of(U, V.g.q[j]) >= 0 && V.prev[j] != u) sole = false;
+                if (!sole) continue;
+                // (4) acyclicity, by rule A (other preds of v precede u) or
+                //     rule B (other succs of u follow v)
+                bool ruleA = true, ruleB = true;
+                for (int j = 0; j < V.g.k; ++j) {
+                    const int p = V.prev[j];
+                    if (p >= 0 && p != u && pos[p] > pos[u]) ruleA = false;
+                }
+                for (int j = 0; j < U.g.k; ++j) {
+                    const int s = U.next[j];
+                    if (s >= 0 && s != v && pos[s] < pos[v]) ruleB = false;
+                }
+                if (!ruleA && !ruleB) continue;
+                // (2) width
+                bool ok = false;
+                FGate f = fuse_pair(U.g, V.g, o.kmax, ok);
+                if (!ok) continue;
+                // (5) arithmetic does not grow beyond what the merge saves
+                if (o.cost_aware > 0 && op_fma(f) > op_fma(U.g) + op_fma(V.g) + o.sigma) continue;
+                // merge v into u: relink the per-qubit lines
+                int nprev[kMaxK], nnext[kMaxK];
+                for (int j = 0; j < f.k; ++j) {
+                    const int x = f.q[j];
+                    const int su = slot_of(U, x), sv = slot_of(V, x);
+                    if (su >= 0 && sv >= 0) {
+                        nprev[j] = U.prev[su];
+                        nnext[j] = V.next[sv];
+                    } else if (su >= 0) {
+                        nprev[j] = U.prev[su];
+                        nnext[j] = U.next[su];
+                    } else {
+                        nprev[j] = V.prev[sv];
+                        nnext[j] = V.next[sv];
+                    }
+                }
+                for (int j = 0; j < f.k; ++j) {
+                    const int x = f.q[j];
+                    if (nprev[j] >= 0) {
+                        Node& P = nodes[nprev[j]];
+                        P.next[slot_of(P, x)] = u;
+                    }
+                    if (nnext[j] >= 0) {
+                        Node& S = nodes[nnext[j]];
+                        S.prev[slot_of(S, x)] = u;
+                    }
+                }
+                U.g = f;
+                for (int j = 0; j < f.k; ++j) {
+                    U.prev[j] = nprev[j];
+                    U.next[j] = nnext[j];
+                }
+                V.alive = false;
+                if (!ruleA) pos[u] = pos[v];  // rule B: the fused node takes v's slot
+                changed = true;
+                break;
+            }
+        }
+    }
+}
+
+}  // namespace
+
+bool make_plan(int n, int dtype, const std::vector<InGate>& gates, const PlanOpts& o,
+               HostPlan& P, std::string& err)
+{
+    P = HostPlan();
+    P.n = n;
+    P.dtype = dtype;
+    P.o = o;
+    P.gates_in = gates.size();
+    if (o.kmax < 1 || o.kmax > kMaxK) { err = "kmax must be in [1, 5]"; return false; }
+    if (o.low_qubits < 1 || o.low_qubits > kLogThreads) { err = "low_qubits must be in [1, 8]"; return false; }
+    if (o.tile_qubits < o.low_qubits + 1 || o.tile_qubits < kMaxK + 1 || o.tile_qubits > kMaxTileQubits) {
+        err = "tile_qubits must be in [max(low_qubits+1, 6), 13]";
+        return false;
+    }
+
+    // ---- DAG (Section 5.1): immediate predecessor per qubit
+    std::vector<Node> nodes(gates.size());
+    std::vector<int> last(n, -1);
+    for (size_t i = 0; i < gates.size(); ++i) {
+        Node& nd = nodes[i];
+        nd.g = canonical(gates[i], (int)i);
+        for (int j = 0; j < nd.g.k; ++j) {
+            const int x = nd.g.q[j];
+            nd.prev[j] = last[x];
+            nd.next[j] = -1;
+            if (last[x] >= 0) {
+                Node& p = nodes[last[x]];
+                p.next[slot_of(p, x)] = (int)i;
+            }
+            last[x] = (int)i;
+        }
+    }
+
+    // ---- Algorithm 2
+    if (o.fuse) run_fusion(nodes, o);
+    for (const int v : topo_order(nodes))
+        if (!is_identity(nodes[v].g)) P.fused.push_back(nodes[v].g);
+
+    // ---- pass scheduling
+    const int F = (int)P.fused.size();
+    const bool whole = o.fuse && n <= o.whole_state_max;
+    const int m = whole ? n : std::min(o.tile_qubits, n);
+    const int L = std::min(o.low_qubits, m);
+    std::vector<char> done(F, 0);
+    int remaining = F;
+    const unsigned long long all = (n >= 64) ? ~0ull : ((1ull << n) - 1);
+    while (remaining > 0) {
+        PassPlan pp;
+        int Lp = L;   // low qubits kept in this pass's tile
+        unsigned long long A = (L >= 64) ? ~0ull : ((1ull << L) - 1);
+        if (whole) A = all;
+        unsigned long long blocked = 0;
+        double budget = o.pass_budget;
+        for (int i = 0; i < F; ++i) {
+            if (done[i]) continue;
+            const FGate& g = P.fused[i];
+            unsigned long long gm = 0;
+            for (int j = 0; j < g.k; ++j) gm |= 1ull << g.q[j];
+            if (gm & blocked) { blocked |= gm; continue; }
+            const double c = op_fma(g) + o.sigma;
+            const bool limit_ops = o.max_ops_per_pass > 0 && (int)pp.ops.size() >= o.max_ops_per_pass;
+            const bool fits_budget = whole || o.pass_budget < 0 || c <= budget || pp.ops.empty();
+            unsigned long long nA = (g.kind == OP_DIAG) ? A : (A | gm);
+            if (pp.ops.empty() && __builtin_popcountll(nA) > m) {
+                // a gate wider than the tile's free slots opens a pass with fewer low qubits
+                while (Lp > 0 && __builtin_popcountll(gm | ((1ull << Lp) - 1)) > m) --Lp;
+                A = (1ull << Lp) - 1;
+                nA = A | gm;
+            }
+            const bool fits_tile = __builtin_popcountll(nA) <= m;
+            if (!limit_ops && fits_budget && fits_tile) {
+                A = nA;
+                pp.ops.push_back(i);
+                done[i] = 1;
+                --remaining;
+                budget -= c;
+                pp.cost += c;
+            } else {
+                blocked |= gm;
+                if ((blocked & all) == all) break;
+            }
+        }
+        // fill the tile up to m qubits with the lowest unused qubits (longer runs)
+        for (int b = 0; b < n && __builtin_popcountll(A) < m; ++b) A |= 1ull << b;
+        for (int b = 0; b < n; ++b)
+            if ((A >> b) & 1) pp.active.push_back(b);
+        pp.low = Lp;
+        if (pp.ops.empty()) { err = "internal: a gate does not fit any tile"; return false; }
+        P.passes.push_back(pp);
+    }
+
+    // ---- device tables
+    for (const PassPlan& pp : P.passes) {
+        PassArgs a{};
+        a.m = (int)pp.active.size();
+        a.L = pp.low;
+        for (int i = L; i < a.m; ++i) a.hstride[i - L] = 1ll << pp.active[i];
+        a.nruns = 0;
+        {
+            unsigned long long A = 0;
+            for (int b : pp.active) A |= 1ull << b;
+            int b = 0;
+            while (b < n) {
+                if ((A >> b) & 1) { ++b; continue; }
+                int s = b;
+                while (b < n && !((A >> b) & 1)) ++b;
+                a.run_pos[a.nruns] = s;
+                a.run_len[a.nruns] = b - s;
+                ++a.nruns;
+            }
+        }
+        a.op_begin = (int)P.ops.size();
+        a.op_count = (int)pp.ops.size();
+        for (const int fi : pp.ops) {
+            const FGate& g = P.fused[fi];
+            DevOp d{};
+            d.kind = g.kind;
+            d.k = g.k;
+            for (int j = 0; j < kMaxK; ++j) { d.lpos[j] = -1; d.gbit[j] = 0; }
+            for (int j = 0; j < g.k; ++j) {
+                d.gbit[j] = g.q[j];
+                auto it = std::find(pp.active.begin(), pp.active.end(), g.q[j]);
+                d.lpos[j] = (it == pp.active.end()) ? -1 : (int)(it - pp.active.begin());
+            }
+            const int dd = 1 << g.k;
+            d.off = (int)P.pool.size();
+            if (g.kind == OP_DENSE) {
+                P.pool.insert(P.pool.end(), g.m.begin(), g.m.end());
+                ++P.dense_ops;
+            } else if (g.kind == OP_DIAG) {
+                for (int r = 0; r < dd; ++r) P.pool.push_back(g.m[(size_t)r * dd + r]);
+                ++P.diag_ops;
+            } else {
+                d.ioff = (int)P.ipool.size();
+                d.flags = 0;
+                for (int r = 0; r < dd; ++r) {
+                    int src = 0;
+                    for (int c = 0; c < dd; ++c)
+                        if (g.m[(size_t)r * dd + c] != cd(0, 0)) src = c;
+                    const cd ph = g.m[(size_t)r * dd + src];
+                    P.ipool.push_back(src);
+                    P.pool.push_back(ph);
+                    if (ph != cd(1, 0)) d.flags = 1;
+                }
+                ++P.perm_ops;
+            }
+            P.fma_per_amp += op_fma(g);
+            P.ops.push_back(d);
+        }
+        P.pargs.push_back(a);
+        P.pgrid.push_back(1ll << (n - a.m));
+    }
+    return true;
+}
+
+}  // namespace qsv

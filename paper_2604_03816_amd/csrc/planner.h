@@ -1,0 +1,83 @@
+// planner.h -- host-side circuit planner of libqsv: DAG construction (Section 5.1),
+// DAG gate fusion (Section 5.2, Algorithm 2, Eq. 9) and HBM pass scheduling.
+#pragma once
+#include <complex>
+#include <string>
+#include <vector>
+
+#include "qsv_internal.h"
+
+namespace qsv {
+
+using cd = std::complex<double>;
+
+// A gate as given by the caller, already validated: dense 2^k x 2^k row-major matrix,
+// local bit j <-> t[j].
+struct InGate {
+    int k;
+    int t[kMaxK];
+    std::vector<cd> m;
+};
+
+// A fused gate: targets ascending, dense matrix with local bit j <-> q[j].
+struct FGate {
+    int k = 0;
+    int q[kMaxK] = {0, 0, 0, 0, 0};
+    std::vector<cd> m;
+    int kind = OP_DENSE;  // OP_DENSE, OP_DIAG or OP_PERM (classified from the matrix)
+    int first = 0;        // smallest circuit index among the fused members
+    int members = 1;
+};
+
+struct PlanOpts {
+    int fuse = 1;
+    int kmax = 5;
+    int cost_aware = 1;
+    int tile_qubits = 12;
+    int low_qubits = 4;
+    int whole_state_max = 12;  // n <= this: the whole state is one on-chip tile
+    double pass_budget = 160;  // FMA per amplitude per pass (<0: unlimited)
+    double sigma = 8;          // per-op on-chip cost in FMA-per-amplitude units
+    int max_ops_per_pass = 0;  // 0: no limit
+};
+
+struct PassPlan {
+    std::vector<int> active;  // physical qubits held by the tile, ascending
+    std::vector<int> ops;     // indices into HostPlan::fused
+    int low = 0;              // qubits 0..low-1 are the contiguous low part of the tile
+    double cost = 0;
+};
+
+struct HostPlan {
+    int n = 0;
+    int dtype = 0;
+    PlanOpts o;
+    size_t gates_in = 0;
+    std::vector<FGate> fused;
+    std::vector<PassPlan> passes;
+    // device-format tables
+    std::vector<DevOp> ops;
+    std::vector<PassArgs> pargs;
+    std::vector<long long> pgrid;  // tiles per pass
+    std::vector<cd> pool;
+    std::vector<int> ipool;
+    // stats
+    size_t dense_ops = 0, diag_ops = 0, perm_ops = 0;
+    double fma_per_amp = 0;
+};
+
+// Arithmetic cost of one op on chip, in FMA per amplitude (excluding sigma).
+double op_fma(const FGate& g);
+
+// Classifies a dense matrix: OP_DIAG when every off-diagonal entry is exactly zero,
+// OP_PERM when every row and column holds exactly one nonzero, else OP_DENSE.
+int classify(const std::vector<cd>& m, int k);
+
+// Runs fusion (when o.fuse) and pass scheduling; fills every field of `out`.
+bool make_plan(int n, int dtype, const std::vector<InGate>& gates, const PlanOpts& o,
+               HostPlan& out, std::string& err);
+
+// Default options for a dtype (0 = complex64, 1 = complex128).
+PlanOpts default_opts(int dtype);
+
+}  // namespace qsv

@@ -1,0 +1,93 @@
+// qsv_internal.h -- structures shared by the host planner, the C-ABI layer and the
+// HIP kernels of libqsv.so.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace qsv {
+
+constexpr int kMaxK = 5;            // widest fused gate (dense / permutation)
+constexpr int kMaxDiagK = 5;        // widest diagonal op
+constexpr int kThreads = 256;       // threads per tile workgroup
+constexpr int kLogThreads = 8;
+constexpr int kMaxTileQubits = 13;  // 2^13 amplitudes: 64 KiB of complex64
+constexpr int kMaxQubits = 34;
+
+enum OpKind : int { OP_DENSE = 0, OP_DIAG = 1, OP_PERM = 2 };
+
+// One op applied to a tile held on chip.  Targets are listed in the order of the
+// op's local basis bits (ascending physical qubit).
+struct DevOp {
+    int kind;
+    int k;
+    int lpos[kMaxK];    // tile-local bit of each target, or -1 (diagonal op, qubit outside the tile)
+    int gbit[kMaxK];    // physical qubit of each target
+    int off;            // offset into the complex pool: dense 4^k, diagonal 2^k, permutation 2^k phases
+    int ioff;           // permutation: offset into the int pool (2^k source rows)
+    int flags;          // permutation: 1 when some phase differs from 1
+    int pad;
+};
+
+// Everything a pass kernel needs to place its tile in the state vector.
+// Local tile index bits 0..L-1 are physical bits 0..L-1; local bits L..m-1 are the
+// other tile qubits in ascending order with physical strides hstride[].  The tile
+// number is deposited into the remaining (free) physical bits, which form nruns
+// maximal runs (run_pos, run_len).
+struct PassArgs {
+    long long hstride[kMaxTileQubits];
+    int run_pos[kMaxQubits];
+    int run_len[kMaxQubits];
+    int nruns;
+    int m;
+    int L;
+    int op_begin;
+    int op_count;
+};
+
+// Work list for the expectation kernel: up to kMaxTermsPerLaunch Pauli strings whose
+// X/Y supports all lie inside the tile.
+constexpr int kMaxTermsPerLaunch = 32;
+struct TermArgs {
+    int nterms;
+    int xloc[kMaxTermsPerLaunch];          // X/Y support as tile-local bit mask
+    int zloc[kMaxTermsPerLaunch];          // Z/Y support inside the tile, local bit mask
+    long long zglob[kMaxTermsPerLaunch];   // Z/Y support outside the tile, physical mask
+    int ny[kMaxTermsPerLaunch];            // number of Y factors (phase i^ny)
+};
+
+// A weighted Pauli sum applied to a state (co-state of the adjoint method).
+constexpr int kMaxPauliApply = 64;
+struct PauliSumArgs {
+    int nterms;
+    int ny[kMaxPauliApply];
+    long long x[kMaxPauliApply];
+    long long z[kMaxPauliApply];
+    double coeff[kMaxPauliApply];
+};
+
+// Marginal probabilities: thread (o, chunk) sums |alpha|^2 over the indices whose
+// bits at the measured qubits spell o, for the chunk-th range of the other bits.
+struct MargArgs {
+    int n, m;
+    int q[kMaxQubits];      // measured qubits, output bit j <-> q[j]
+    int rest[kMaxQubits];   // the other qubits, ascending
+    long long chunk;        // rest-values per thread
+    long long nchunks;
+};
+
+// Launchers (kernels.hip).  dtype 0 = complex64, 1 = complex128.
+hipError_t launch_pass(int dtype, void* st, const PassArgs& a, long long grid, const DevOp* ops,
+                       const void* pool, const int* ipool, hipStream_t s);
+hipError_t launch_init_zero(int dtype, void* st, long long N, hipStream_t s);
+hipError_t launch_zero(int dtype, void* st, long long N, hipStream_t s);
+int norm_grid(long long N);
+hipError_t launch_norm(int dtype, const void* st, long long N, double* partial, int grid, hipStream_t s);
+hipError_t launch_expval(int dtype, const void* sa, const void* sb, const PassArgs& a, const TermArgs& t,
+                         long long ntiles, int grid, double* partial, hipStream_t s);
+hipError_t launch_pauli_apply(int dtype, const void* in, void* out, long long N, const PauliSumArgs& p,
+                              int accumulate, hipStream_t s);
+hipError_t launch_probs_full(int dtype, const void* st, long long N, void* out, hipStream_t s);
+hipError_t launch_probs_marg(int dtype, const void* st, const MargArgs& a, double* partial, double* out,
+                             hipStream_t s);
+
+}  // namespace qsv

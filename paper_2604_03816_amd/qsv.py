@@ -1,0 +1,404 @@
+"""ctypes binding of libqsv.so (include/qsv.h).  Argument marshalling only: every
+step of the simulation runs inside the library (host planner + HIP kernels).
+
+PyTorch supplies device memory and streams: a :class:`State` owns a torch tensor
+of dtype complex64 / complex128 on a ROCm device and hands its data pointer and the
+current torch stream to ``qsv_alloc``.  If libqsv.so has not been built the import
+fails -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_build", "libqsv.so")
+
+QSV_OK, QSV_E_ARG, QSV_E_OOM, QSV_E_DEVICE, QSV_E_UNSUPPORTED = 0, 1, 2, 3, 4
+C64, C128 = 0, 1
+_DT = {"c64": C64, "c128": C128, "complex64": C64, "complex128": C128}
+_STATUS = {1: "QSV_E_ARG", 2: "QSV_E_OOM", 3: "QSV_E_DEVICE", 4: "QSV_E_UNSUPPORTED"}
+
+
+class QSVError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (_STATUS.get(status, str(status)), msg))
+        self.status = status
+
+
+class Gate(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int), ("targets", ctypes.c_int * 5), ("diag", ctypes.c_int),
+                ("mat", ctypes.POINTER(ctypes.c_double))]
+
+
+class PlanOpts(ctypes.Structure):
+    _fields_ = [("fuse", ctypes.c_int), ("kmax", ctypes.c_int), ("cost_aware", ctypes.c_int),
+                ("tile_qubits", ctypes.c_int), ("low_qubits", ctypes.c_int),
+                ("pass_budget", ctypes.c_double)]
+
+
+class PlanStats(ctypes.Structure):
+    _fields_ = [("gates_in", ctypes.c_size_t), ("fused_out", ctypes.c_size_t), ("passes", ctypes.c_size_t),
+                ("dense_ops", ctypes.c_size_t), ("diag_ops", ctypes.c_size_t), ("perm_ops", ctypes.c_size_t),
+                ("fma_per_amp", ctypes.c_double), ("hbm_bytes", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f[0]: getattr(self, f[0]) for f in self._fields_}
+
+
+class PauliTerm(ctypes.Structure):
+    _fields_ = [("coeff", ctypes.c_double), ("n", ctypes.c_int), ("qubits", ctypes.POINTER(ctypes.c_int)),
+                ("paulis", ctypes.c_char_p)]
+
+
+class COp(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("k", ctypes.c_int), ("targets", ctypes.c_int * 5),
+                ("mat", ctypes.POINTER(ctypes.c_double)), ("param", ctypes.c_int)]
+
+
+EXPORTS = [
+    "qsv_last_error", "qsv_version", "qsv_alloc", "qsv_free", "qsv_reset", "qsv_info", "qsv_get_state",
+    "qsv_set_state", "qsv_gate_matrix", "qsv_plan_create", "qsv_plan_free", "qsv_plan_get_stats",
+    "qsv_plan_fused_gate", "qsv_plan_pass_info", "qsv_plan_pass_ops", "qsv_plan_apply", "qsv_plan_apply_range",
+    "qsv_apply_fused", "qsv_sync", "qsv_norm", "qsv_expval_pauli", "qsv_probs", "qsv_adjoint_grad",
+]
+
+_LIB = None
+
+
+def lib():
+    """Load libqsv.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libqsv.so is not built (%s); run paper_2604_03816_amd/build.py" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i, sz, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(ctypes.c_double)
+    L.qsv_last_error.restype = ctypes.c_char_p
+    L.qsv_version.restype = ctypes.c_char_p
+    L.qsv_alloc.argtypes = [i, i, vp, sz, vp, ctypes.POINTER(vp)]
+    L.qsv_free.argtypes = [vp]
+    L.qsv_reset.argtypes = [vp]
+    L.qsv_info.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(vp)]
+    L.qsv_get_state.argtypes = [vp, vp]
+    L.qsv_set_state.argtypes = [vp, vp]
+    L.qsv_gate_matrix.argtypes = [ctypes.c_char_p, dp, ctypes.POINTER(i), dp]
+    L.qsv_plan_create.argtypes = [i, i, ctypes.POINTER(Gate), sz, ctypes.POINTER(PlanOpts), ctypes.POINTER(vp)]
+    L.qsv_plan_free.argtypes = [vp]
+    L.qsv_plan_get_stats.argtypes = [vp, ctypes.POINTER(PlanStats)]
+    L.qsv_plan_fused_gate.argtypes = [vp, sz, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i), dp]
+    L.qsv_plan_pass_info.argtypes = [vp, sz, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]
+    L.qsv_plan_pass_ops.argtypes = [vp, sz, ctypes.POINTER(i)]
+    L.qsv_plan_apply.argtypes = [vp, vp]
+    L.qsv_plan_apply_range.argtypes = [vp, vp, sz, sz]
+    L.qsv_apply_fused.argtypes = [vp, ctypes.POINTER(Gate), sz, ctypes.POINTER(PlanOpts), ctypes.POINTER(PlanStats)]
+    L.qsv_sync.argtypes = [vp]
+    L.qsv_norm.argtypes = [vp, dp]
+    L.qsv_expval_pauli.argtypes = [vp, ctypes.POINTER(PauliTerm), sz, dp, dp]
+    L.qsv_probs.argtypes = [vp, ctypes.POINTER(i), i, vp, i]
+    L.qsv_adjoint_grad.argtypes = [i, i, ctypes.POINTER(COp), sz, dp, i, i, ctypes.POINTER(PauliTerm), sz,
+                                   dp, dp, vp]
+    _LIB = L
+    return L
+
+
+def check(status: int) -> None:
+    if status != QSV_OK:
+        raise QSVError(status, lib().qsv_last_error().decode())
+
+
+def version() -> str:
+    return lib().qsv_version().decode()
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+# ------------------------------------------------------------------ gates
+
+def gate_matrix(name: str, params: Sequence[float] = ()) -> np.ndarray:
+    """The library's Eq. 4 gate matrix (complex128, 2^k x 2^k)."""
+    p = np.zeros(4, dtype=np.float64)
+    p[: len(params)] = params
+    out = np.zeros(2 * 64, dtype=np.float64)
+    k = ctypes.c_int(0)
+    check(lib().qsv_gate_matrix(name.encode(), _dptr(p), ctypes.byref(k), _dptr(out)))
+    d = 1 << k.value
+    return out[: 2 * d * d].view(np.complex128).reshape(d, d).copy()
+
+
+class GateList:
+    """A circuit marshalled into a ctypes qsv_gate array (owns the matrix buffers)."""
+
+    def __init__(self, ops: Iterable):
+        ops = list(ops)
+        self._mats: List[np.ndarray] = []
+        self.arr = (Gate * max(1, len(ops)))()
+        self.n = len(ops)
+        for i, op in enumerate(ops):
+            if op.name == "U":
+                m = np.ascontiguousarray(op.matrix, dtype=np.complex128)
+            else:
+                m = gate_matrix(op.name, op.params)
+            k = len(op.qubits)
+            if not 1 <= k <= 5:
+                raise ValueError("op %d: a gate acts on 1 to 5 qubits, got %d" % (i, k))
+            if m.shape != (1 << k, 1 << k):
+                raise ValueError("op %d: matrix shape %s does not match %d targets" % (i, m.shape, k))
+            buf = np.ascontiguousarray(m.reshape(-1)).view(np.float64).copy()
+            self._mats.append(buf)
+            g = self.arr[i]
+            g.k = k
+            for j, q in enumerate(op.qubits):
+                g.targets[j] = int(q)
+            g.diag = 0
+            g.mat = _dptr(buf)
+
+
+def _opts(fuse=True, kmax=0, cost_aware=0, tile_qubits=0, low_qubits=0, pass_budget=0.0) -> PlanOpts:
+    o = PlanOpts()
+    o.fuse = 1 if fuse else 0
+    o.kmax = kmax
+    o.cost_aware = cost_aware
+    o.tile_qubits = tile_qubits
+    o.low_qubits = low_qubits
+    o.pass_budget = pass_budget
+    return o
+
+
+class Plan:
+    """qsv_plan: fused + scheduled circuit for one (n, dtype)."""
+
+    def __init__(self, n: int, dtype: str, ops: Iterable, **opts):
+        self.n = n
+        self.dtype = dtype
+        gl = ops if isinstance(ops, GateList) else GateList(ops)
+        h = ctypes.c_void_p()
+        o = _opts(**opts)
+        check(lib().qsv_plan_create(n, _DT[dtype], gl.arr, gl.n, ctypes.byref(o), ctypes.byref(h)))
+        self.h = h
+
+    def stats(self) -> dict:
+        st = PlanStats()
+        check(lib().qsv_plan_get_stats(self.h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def fused_gates(self) -> List[Tuple[Tuple[int, ...], np.ndarray, bool]]:
+        out = []
+        for i in range(self.stats()["fused_out"]):
+            k, diag = ctypes.c_int(), ctypes.c_int()
+            t = (ctypes.c_int * 5)()
+            m = np.zeros(2 * 1024, dtype=np.float64)
+            check(lib().qsv_plan_fused_gate(self.h, i, ctypes.byref(k), t, ctypes.byref(diag), _dptr(m)))
+            d = 1 << k.value
+            out.append((tuple(t[:k.value]), m[: 2 * d * d].view(np.complex128).reshape(d, d).copy(), bool(diag.value)))
+        return out
+
+    def passes(self) -> List[Tuple[Tuple[int, ...], Tuple[int, ...]]]:
+        """Per pass: (fused-gate indices in application order, tile qubits)."""
+        out = []
+        for i in range(self.stats()["passes"]):
+            nops, nact = ctypes.c_int(), ctypes.c_int()
+            act = (ctypes.c_int * 40)()
+            check(lib().qsv_plan_pass_info(self.h, i, ctypes.byref(nops), ctypes.byref(nact), act))
+            idx = (ctypes.c_int * max(1, nops.value))()
+            check(lib().qsv_plan_pass_ops(self.h, i, idx))
+            out.append((tuple(idx[: nops.value]), tuple(act[: nact.value])))
+        return out
+
+    def free(self):
+        if getattr(self, "h", None):
+            lib().qsv_plan_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ observables
+
+class TermList:
+    def __init__(self, terms):
+        terms = list(terms)
+        self._keep = []
+        self.arr = (PauliTerm * max(1, len(terms)))()
+        self.n = len(terms)
+        for i, (c, string) in enumerate(terms):
+            q = (ctypes.c_int * max(1, len(string)))(*[int(s[0]) for s in string])
+            p = ctypes.c_char_p("".join(s[1] for s in string).encode())
+            self._keep += [q, p]
+            t = self.arr[i]
+            t.coeff = float(c)
+            t.n = len(string)
+            t.qubits = ctypes.cast(q, ctypes.POINTER(ctypes.c_int))
+            t.paulis = p
+
+
+# ------------------------------------------------------------------ states
+
+class State:
+    """A 2^n amplitude state in a torch tensor on a ROCm device, registered with libqsv.
+
+    The state starts as |0...0>.  All device work runs on the torch stream that is
+    current when the State is created (or the one passed in)."""
+
+    def __init__(self, n: int, dtype: str = "c64", device: str = "cuda:0", stream=None):
+        import torch
+        self.n = n
+        self.dtype = dtype
+        tdt = torch.complex64 if _DT[dtype] == C64 else torch.complex128
+        self.tensor = torch.empty(1 << n, dtype=tdt, device=device)
+        with torch.cuda.device(self.tensor.device):
+            s = stream if stream is not None else torch.cuda.current_stream(self.tensor.device)
+            self.stream = s
+            h = ctypes.c_void_p()
+            check(lib().qsv_alloc(n, _DT[dtype], ctypes.c_void_p(self.tensor.data_ptr()),
+                                  self.tensor.numel() * self.tensor.element_size(),
+                                  ctypes.c_void_p(s.cuda_stream), ctypes.byref(h)))
+        self.h = h
+
+    # -- application
+    def apply(self, ops, **opts) -> dict:
+        gl = ops if isinstance(ops, GateList) else GateList(ops)
+        st = PlanStats()
+        o = _opts(**opts)
+        check(lib().qsv_apply_fused(self.h, gl.arr, gl.n, ctypes.byref(o), ctypes.byref(st)))
+        return st.as_dict()
+
+    def apply_plan(self, plan: Plan, first: int = None, count: int = None) -> None:
+        if first is None:
+            check(lib().qsv_plan_apply(self.h, plan.h))
+        else:
+            check(lib().qsv_plan_apply_range(self.h, plan.h, first, count))
+
+    def reset(self):
+        check(lib().qsv_reset(self.h))
+
+    def sync(self):
+        check(lib().qsv_sync(self.h))
+
+    # -- data movement
+    def get(self) -> np.ndarray:
+        out = np.empty(1 << self.n, dtype=np.complex64 if _DT[self.dtype] == C64 else np.complex128)
+        check(lib().qsv_get_state(self.h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def set(self, host: np.ndarray) -> None:
+        want = np.complex64 if _DT[self.dtype] == C64 else np.complex128
+        a = np.ascontiguousarray(host, dtype=want)
+        if a.size != 1 << self.n:
+            raise ValueError("size mismatch")
+        check(lib().qsv_set_state(self.h, a.ctypes.data_as(ctypes.c_void_p)))
+
+    # -- reductions
+    def norm(self) -> float:
+        out = ctypes.c_double()
+        check(lib().qsv_norm(self.h, ctypes.byref(out)))
+        return out.value
+
+    def expval(self, terms, per_term: bool = False):
+        tl = terms if isinstance(terms, TermList) else TermList(terms)
+        per = np.zeros(max(1, tl.n), dtype=np.float64)
+        tot = ctypes.c_double()
+        check(lib().qsv_expval_pauli(self.h, tl.arr, tl.n, _dptr(per), ctypes.byref(tot)))
+        return (tot.value, per[: tl.n].copy()) if per_term else tot.value
+
+    def probs(self, qubits: Optional[Sequence[int]] = None, out=None):
+        """Full distribution (qubits None) in the state's real precision, or the marginal
+        over ``qubits`` in float64.  ``out`` may be a device torch tensor."""
+        if qubits is None:
+            m, qp = self.n, None
+            full = True
+        else:
+            m = len(qubits)
+            qa = (ctypes.c_int * m)(*[int(q) for q in qubits])
+            qp = ctypes.cast(qa, ctypes.POINTER(ctypes.c_int))
+            full = list(qubits) == list(range(self.n))
+        rdt = (np.float32 if _DT[self.dtype] == C64 else np.float64) if full else np.float64
+        if out is not None:
+            check(lib().qsv_probs(self.h, qp, m, ctypes.c_void_p(out.data_ptr()), 1))
+            return out
+        host = np.empty(1 << m, dtype=rdt)
+        check(lib().qsv_probs(self.h, qp, m, host.ctypes.data_as(ctypes.c_void_p), 0))
+        return host
+
+    def free(self):
+        if getattr(self, "h", None):
+            lib().qsv_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def simulate(n: int, ops, dtype: str = "c64", **opts) -> State:
+    s = State(n, dtype)
+    s.apply(ops, **opts)
+    return s
+
+
+# ------------------------------------------------------------------ adjoint gradients
+
+_ROT = {"RX": 1, "RY": 2, "RZ": 3}
+
+
+class OpList:
+    """A parameterised circuit marshalled into a ctypes qsv_op array: RX/RY/RZ ops that
+    carry a parameter index become kind 1/2/3; every other op is a fixed gate."""
+
+    def __init__(self, template):
+        template = list(template)
+        self._mats = []
+        self.arr = (COp * max(1, len(template)))()
+        self.n = len(template)
+        for i, op in enumerate(template):
+            c = self.arr[i]
+            for j, q in enumerate(op.qubits):
+                c.targets[j] = int(q)
+            if op.param is not None:
+                if op.name not in _ROT:
+                    raise ValueError("op %d: only RX/RY/RZ may carry a parameter" % i)
+                c.kind = _ROT[op.name]
+                c.k = 1
+                c.param = int(op.param)
+            else:
+                m = np.ascontiguousarray(op.matrix, dtype=np.complex128) if op.name == "U" \
+                    else gate_matrix(op.name, op.params)
+                buf = np.ascontiguousarray(m.reshape(-1)).view(np.float64).copy()
+                self._mats.append(buf)
+                c.kind = 0
+                c.k = len(op.qubits)
+                c.mat = _dptr(buf)
+                c.param = -1
+
+
+def adjoint_grad(n: int, template, params, terms, dtype: str = "c128", stream=None):
+    """Energies E_b = <psi(theta_b)|H|psi(theta_b)> and dE_b/dtheta by the adjoint method.
+
+    params: (B, P) or (P,) array of angles; terms: Pauli sum [(coeff, ((q, 'X'), ...)), ...].
+    Returns (E[B], G[B, P]) as float64 numpy arrays ((P,) inputs give E scalar, G[P])."""
+    import torch
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    single = p.ndim == 1
+    if single:
+        p = p[None, :]
+    B, P = p.shape
+    ol = template if isinstance(template, OpList) else OpList(template)
+    tl = terms if isinstance(terms, TermList) else TermList(terms)
+    E = np.zeros(B, dtype=np.float64)
+    G = np.zeros((B, P), dtype=np.float64)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    check(lib().qsv_adjoint_grad(n, _DT[dtype], ol.arr, ol.n, _dptr(p), B, P, tl.arr, tl.n, _dptr(E), _dptr(G),
+                                 ctypes.c_void_p(s.cuda_stream)))
+    return (E[0], G[0]) if single else (E, G)

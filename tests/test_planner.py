@@ -1,0 +1,220 @@
+"""Host-side tests of libqsv (no GPU): the C ABI loads and exports what include/qsv.h
+declares; the library's gate set matches the oracle's; DAG fusion (Algorithm 2 with the
+acyclicity fix) and pass scheduling preserve the circuit product (Eq. 10), which the
+FP64 oracle checks by replaying the plan's fused gates in pass order."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_03816_amd import circuits as C
+from paper_2604_03816_amd import qsv
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def rand_unitary(d, rng):
+    z = rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d))
+    q, r = np.linalg.qr(z)
+    return q * (np.diag(r) / np.abs(np.diag(r)))
+
+
+def plan_replay(n, plan):
+    """Apply the plan's fused gates with the oracle, in the order the passes apply them."""
+    fused = plan.fused_gates()
+    psi = oracle.zero_state(n)
+    order = []
+    for idx, active in plan.passes():
+        for i in idx:
+            targets, m, diag = fused[i]
+            if not diag:
+                assert set(targets) <= set(active), "dense/perm op outside its tile"
+            oracle.apply(psi, m, targets)
+            order.append(i)
+    assert sorted(order) == list(range(len(fused))), "every fused gate exactly once"
+    return psi
+
+
+# ------------------------------------------------------------------ the ABI
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "qsv.h")).read()
+    declared = set(re.findall(r"\b(qsv_[a-z_]+)\s*\(", hdr))
+    L = qsv.lib()
+    missing = [name for name in sorted(declared) if not hasattr(L, name)]
+    assert not missing, missing
+    assert declared == set(qsv.EXPORTS)
+    assert qsv.version().startswith("qsv")
+
+
+@pytest.mark.parametrize("name,params", [("I", ()), ("X", ()), ("Y", ()), ("Z", ()), ("H", ()), ("S", ()),
+                                         ("SDG", ()), ("T", ()), ("TDG", ()), ("RX", (0.7,)), ("RY", (-2.1,)),
+                                         ("RZ", (4.0,)), ("U3", (0.3, 1.1, -0.4)), ("CNOT", ()), ("CZ", ()),
+                                         ("SWAP", ()), ("TOFFOLI", ())])
+def test_gate_set_matches_oracle(name, params):
+    assert np.allclose(qsv.gate_matrix(name, params), oracle.gate_matrix(name, params), atol=1e-15)
+
+
+def test_argument_errors():
+    with pytest.raises(qsv.QSVError) as e:
+        qsv.gate_matrix("NOPE")
+    assert e.value.status == qsv.QSV_E_ARG
+    bad = [C.Op("CNOT", (1, 1))]
+    with pytest.raises(qsv.QSVError):
+        qsv.Plan(4, "c64", bad)
+    with pytest.raises(qsv.QSVError):
+        qsv.Plan(4, "c64", [C.Op("H", (4,))])
+    with pytest.raises(qsv.QSVError):
+        qsv.Plan(40, "c64", [C.Op("H", (0,))])
+    six = C.Op("U", tuple(range(6)), matrix=np.eye(64, dtype=complex))
+    with pytest.raises(ValueError):
+        qsv.Plan(8, "c64", [six])  # the binding's Gate struct holds 5 targets
+    with pytest.raises(qsv.QSVError):
+        qsv.Plan(16, "c64", C.ghz(16), tile_qubits=14)
+    with pytest.raises(qsv.QSVError):
+        qsv.Plan(16, "c64", C.ghz(16), kmax=6)
+
+
+def test_null_arguments_return_errors():
+    L = qsv.lib()
+    assert L.qsv_alloc(10, 0, None, 0, None, None) == qsv.QSV_E_ARG
+    assert L.qsv_plan_create(10, 0, None, 3, None, ctypes.byref(ctypes.c_void_p())) == qsv.QSV_E_ARG
+    assert L.qsv_norm(None, None) == qsv.QSV_E_ARG
+    assert L.qsv_free(None) == qsv.QSV_OK
+
+
+# ------------------------------------------------------------------ fusion soundness (Eq. 9 / Eq. 10)
+
+def _random_gate_circuit(n, count, rng, kmax_gate=3):
+    ops = []
+    for _ in range(count):
+        k = int(rng.integers(1, kmax_gate + 1))
+        qs = tuple(int(q) for q in rng.permutation(n)[:k])
+        ops.append(C.Op("U", qs, matrix=rand_unitary(1 << k, rng)))
+    return ops
+
+
+def test_paper_fusibility_counterexamples_stay_sound():
+    """Gates u{0,1}, w1{1,3}, w2{3,2}, v{0,2}: Algorithm 2's rule (3) alone would merge u
+    and v across w1 and w2; the shorter u{0,1}, w{1,2}, v{0,2} likewise.  The fused plan
+    must still equal the circuit."""
+    rng = np.random.default_rng(8)
+    for qsets in ([(0, 1), (1, 3), (3, 2), (0, 2)], [(0, 1), (1, 2), (0, 2)]):
+        ops = [C.Op("U", q, matrix=rand_unitary(4, rng)) for q in qsets]
+        for kmax in (2, 3, 4, 5):
+            for cost in (1, -1):
+                plan = qsv.Plan(4, "c128", ops, kmax=kmax, cost_aware=cost)
+                ref = oracle.simulate(4, ops)
+                assert np.max(np.abs(plan_replay(4, plan) - ref)) < 1e-13
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("kmax", [1, 2, 3, 5])
+@pytest.mark.parametrize("cost", [1, -1])
+def test_fused_plan_equals_circuit_random(seed, kmax, cost):
+    rng = np.random.default_rng(seed)
+    n = 9
+    ops = _random_gate_circuit(n, 60, rng)
+    plan = qsv.Plan(n, "c128", ops, kmax=max(kmax, 3), cost_aware=cost, tile_qubits=6, low_qubits=2)
+    ref = oracle.simulate(n, ops)
+    assert np.max(np.abs(plan_replay(n, plan) - ref)) < 1e-12
+    for targets, m, diag in plan.fused_gates():
+        assert len(targets) <= max(kmax, 3)
+        assert list(targets) == sorted(targets)
+        off = m - np.diag(np.diag(m))
+        assert diag == (np.max(np.abs(off)) == 0)
+
+
+@pytest.mark.parametrize("circuit", ["brickwork", "hea", "qft", "ghz", "random1q"])
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_plans_for_workload_circuits(circuit, dtype):
+    n = 14
+    ops = {"brickwork": lambda: C.brickwork(n, 12, 4),
+           "hea": lambda: C.bind(C.hea(n, 3, ring=True), C.hea_params(n, 3, seed=2)),
+           "qft": lambda: C.qft(n),
+           "ghz": lambda: C.ghz(n),
+           "random1q": lambda: C.random_1q(n, 5)}[circuit]()
+    ref = oracle.simulate(n, ops)
+    for opts in ({}, {"fuse": False}, {"kmax": 2}, {"cost_aware": -1}, {"tile_qubits": 8, "low_qubits": 3},
+                 {"pass_budget": -1}):
+        plan = qsv.Plan(n, dtype, ops, **opts)
+        st = plan.stats()
+        assert st["gates_in"] == len(ops)
+        if opts.get("fuse", True) is False:
+            assert st["passes"] == st["fused_out"] == len(ops)
+        got = plan_replay(n, plan)
+        assert np.max(np.abs(got - ref)) < 1e-12, opts
+
+
+def test_fusion_reduces_gate_count_and_is_deterministic():
+    n = 20
+    ops = C.qft(n)
+    a = qsv.Plan(n, "c128", ops, kmax=2, cost_aware=-1)
+    b = qsv.Plan(n, "c128", ops, kmax=2, cost_aware=-1)
+    sa, sb = a.stats(), b.stats()
+    assert sa == sb
+    assert sa["fused_out"] < len(ops)
+    fa, fb = a.fused_gates(), b.fused_gates()
+    assert all(x[0] == y[0] and np.array_equal(x[1], y[1]) for x, y in zip(fa, fb))
+    # the brickwork at kmax=5 (pure Algorithm 2) fuses to fewer, wider gates than kmax=2
+    bw = C.brickwork(16, 20, 3)
+    s2 = qsv.Plan(16, "c64", bw, kmax=2, cost_aware=-1).stats()
+    s5 = qsv.Plan(16, "c64", bw, kmax=5, cost_aware=-1).stats()
+    assert s5["fused_out"] < s2["fused_out"] < len(bw)
+
+
+def test_diagonal_gates_merge_and_need_no_tile_capacity():
+    """A CZ ladder is diagonal: it fuses into diagonal ops that may touch qubits outside
+    the pass's tile."""
+    n = 16
+    ops = [C.Op("H", (q,)) for q in range(n)] + [C.Op("CZ", (i, i + 1)) for i in range(n - 1)]
+    ops += [C.Op("H", (q,)) for q in range(n)]
+    # kmax = 1 keeps each CZ a separate diagonal op (no merge into the Hadamards)
+    plan = qsv.Plan(n, "c128", ops, tile_qubits=8, low_qubits=4, kmax=1)
+    st = plan.stats()
+    assert st["diag_ops"] >= 1
+    fused = plan.fused_gates()
+    outside = 0
+    for idx, active in plan.passes():
+        for i in idx:
+            t, m, diag = fused[i]
+            if diag and not set(t) <= set(active):
+                outside += 1
+    assert outside >= 1
+    ref = oracle.simulate(n, ops)
+    assert np.max(np.abs(plan_replay(n, plan) - ref)) < 1e-12
+
+
+def test_identity_products_are_dropped():
+    ops = [C.Op("X", (3,)), C.Op("X", (3,)), C.Op("CNOT", (0, 1)), C.Op("CNOT", (0, 1))]
+    plan = qsv.Plan(5, "c64", ops)
+    assert plan.stats()["fused_out"] == 0
+    assert plan.stats()["passes"] == 0
+
+
+def test_pass_tiles_hold_low_qubits_and_fit():
+    n = 24
+    plan = qsv.Plan(n, "c64", C.brickwork(n, 6, 1))
+    for idx, active in plan.passes():
+        assert len(active) == 12
+        assert set(range(5)) <= set(active)
+
+
+def test_wide_gates_in_narrow_tiles():
+    """A gate whose targets do not fit beside the reserved low qubits opens a pass with
+    fewer low qubits instead of never being scheduled."""
+    rng = np.random.default_rng(3)
+    n = 14
+    ops = [C.Op("U", (13, 12, 11), matrix=rand_unitary(8, rng)),
+           C.Op("U", (9, 13, 7, 12, 10), matrix=rand_unitary(32, rng)),
+           C.Op("U", (0, 13), matrix=rand_unitary(4, rng))]
+    ref = oracle.simulate(n, ops)
+    for tq, lq in ((7, 6), (6, 5), (8, 7), (6, 1)):
+        for fuse in (True, False):
+            plan = qsv.Plan(n, "c64", ops, tile_qubits=tq, low_qubits=lq, fuse=fuse)
+            assert np.max(np.abs(plan_replay(n, plan) - ref)) < 1e-12
+    with pytest.raises(qsv.QSVError):
+        qsv.Plan(n, "c64", ops, tile_qubits=5, low_qubits=2)
