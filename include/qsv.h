@@ -149,6 +149,11 @@ qsv_status qsv_plan_pass_info(qsv_plan p, size_t i, int* n_ops, int* n_active,
  * the order the pass applies them.  fused_idx must hold n_ops ints. */
 qsv_status qsv_plan_pass_ops(qsv_plan p, size_t i, int* fused_idx);
 
+/* Re-enacts the plan's passes on the host, in FP64, with the exact tile placement and
+ * op tables the pass kernel consumes.  state: host array of 2^n complex128 (2^(n+1)
+ * doubles), updated in place.  A checking aid for host-only tests; slow. */
+qsv_status qsv_plan_emulate(qsv_plan p, double* state);
+
 /* Enqueues the plan's passes on the state's stream (Eq. 10: the fused product applied
  * in order).  The plan must match the state's n and dtype.  The plan may be freed
  * only after the stream has finished with it (qsv_sync). */

@@ -217,13 +217,16 @@ int or_probs(const cplx* psi, int n, const int* qubits, int m, double* out)
         for (int i = 0; i < j; ++i) if (qubits[i] == qubits[j]) return -1;
     }
     const int64_t N = (int64_t)1 << n, M = (int64_t)1 << m;
-    for (int64_t o = 0; o < M; ++o) out[o] = 0.0;
+    nsum* acc = (nsum*)calloc((size_t)M, sizeof(nsum));
+    if (!acc) return -1;
     for (int64_t k = 0; k < N; ++k) {
         int64_t o = 0;
         for (int j = 0; j < m; ++j) o |= ((k >> qubits[j]) & 1) << j;
         const double re = creal(psi[k]), im = cimag(psi[k]);
-        out[o] += re * re + im * im;
+        nadd(&acc[o], re * re + im * im);
     }
+    for (int64_t o = 0; o < M; ++o) out[o] = acc[o].s + acc[o].c;
+    free(acc);
     return 0;
 }
 

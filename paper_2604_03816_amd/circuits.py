@@ -39,25 +39,33 @@ class Op:
     param: Optional[int] = None           # index into a parameter vector (rotations)
 
 
-def haar_u2(rng: np.random.Generator) -> np.ndarray:
-    """Haar-random U(2): QR of a complex Gaussian 2x2 with the phases of R's diagonal
-    moved into Q (Mezzadri's correction, without which plain QR is not Haar)."""
-    z = (rng.standard_normal((2, 2)) + 1j * rng.standard_normal((2, 2))) / math.sqrt(2.0)
+def haar_u2(rng: np.random.Generator, count: Optional[int] = None) -> np.ndarray:
+    """Haar-random U(2): QR of a complex Gaussian 2x2 (entries (N(0,1) + i N(0,1))/sqrt 2)
+    with the phases of R's diagonal moved into Q (Mezzadri's correction, without which
+    plain QR is not Haar).  count=None gives one matrix; otherwise an array of `count`
+    matrices whose Gaussians are drawn as one (count, 2, 2, 2) block ordered
+    (matrix, real/imaginary part, row, column)."""
+    c = 1 if count is None else count
+    z = rng.standard_normal((c, 2, 2, 2))
+    z = (z[:, 0] + 1j * z[:, 1]) / math.sqrt(2.0)
     q, r = np.linalg.qr(z)
-    d = np.diag(r)
-    q = q * (d / np.abs(d))[np.newaxis, :]
-    return np.ascontiguousarray(q, dtype=np.complex128)
+    d = np.diagonal(r, axis1=1, axis2=2)
+    q = q * (d / np.abs(d))[:, np.newaxis, :]
+    q = np.ascontiguousarray(q, dtype=np.complex128)
+    return q[0] if count is None else q
 
 
 def brickwork(n: int, depth: int, seed: int) -> List[Op]:
-    """Random brickwork: every layer puts a Haar U(2) on each qubit (ascending), then
-    CNOT(2i, 2i+1) on even layers and CNOT(2i+1, 2i+2) on odd layers (control = lower
-    qubit).  Gate count = depth*n + sum of pairs per layer (290 at n=10, depth 20)."""
+    """Random brickwork: every layer puts a Haar U(2) on each qubit (ascending; one
+    (n, 2, 2, 2) Gaussian block per layer), then CNOT(2i, 2i+1) on even layers and
+    CNOT(2i+1, 2i+2) on odd layers (control = lower qubit).  Gate count =
+    depth*n + sum of pairs per layer (290 at n=10, depth 20)."""
     rng = np.random.default_rng(seed)
     ops: List[Op] = []
     for layer in range(depth):
+        us = haar_u2(rng, n)
         for q in range(n):
-            ops.append(Op("U", (q,), matrix=haar_u2(rng)))
+            ops.append(Op("U", (q,), matrix=us[q]))
         start = layer % 2
         for c in range(start, n - 1, 2):
             ops.append(Op("CNOT", (c, c + 1)))

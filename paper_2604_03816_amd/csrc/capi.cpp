@@ -636,6 +636,82 @@ qsv_status qsv_plan_pass_ops(qsv_plan p, size_t i, int* fused_idx)
     return QSV_OK;
 }
 
+// Host re-enactment of the pass kernel over the device tables (tile placement from the
+// free-bit runs, local offsets from the tile strides, ops by local bit positions), in
+// FP64.  Lets host tests check the tables the GPU consumes without a GPU.
+qsv_status qsv_plan_emulate(qsv_plan p, double* state)
+{
+    if (!p || !state) return fail(QSV_E_ARG, "null argument");
+    const HostPlan& hp = p->hp;
+    cd* st = reinterpret_cast<cd*>(state);
+    for (size_t pi = 0; pi < hp.passes.size(); ++pi) {
+        const PassArgs& a = hp.pargs[pi];
+        const int T = 1 << a.m;
+        std::vector<cd> lds(T);
+        std::vector<long long> off(T);
+        for (int e = 0; e < T; ++e) {
+            long long o = 0;
+            for (int i = 0; i < a.m; ++i)
+                if ((e >> i) & 1) o += (i < a.L) ? (1ll << i) : a.hstride[i - a.L];
+            off[e] = o;
+        }
+        for (long long t = 0; t < hp.pgrid[pi]; ++t) {
+            long long base = 0, rem = t;
+            for (int r = 0; r < a.nruns; ++r) {
+                base |= (rem & ((1ll << a.run_len[r]) - 1)) << a.run_pos[r];
+                rem >>= a.run_len[r];
+            }
+            for (int e = 0; e < T; ++e) lds[e] = st[base + off[e]];
+            for (int oi = 0; oi < a.op_count; ++oi) {
+                const DevOp& op = hp.ops[a.op_begin + oi];
+                const int K = op.k, D = 1 << K;
+                auto roff = [&](int r) {
+                    int o = 0;
+                    for (int j = 0; j < K; ++j)
+                        if ((r >> j) & 1) o += 1 << op.lpos[j];
+                    return o;
+                };
+                if (op.kind == OP_DIAG) {
+                    int gfix = 0;
+                    for (int j = 0; j < K; ++j)
+                        if (op.lpos[j] < 0) gfix |= (int)((base >> op.gbit[j]) & 1) << j;
+                    for (int e = 0; e < T; ++e) {
+                        int idx = gfix;
+                        for (int j = 0; j < K; ++j)
+                            if (op.lpos[j] >= 0) idx |= ((e >> op.lpos[j]) & 1) << j;
+                        lds[e] *= hp.pool[op.off + idx];
+                    }
+                    continue;
+                }
+                for (int j = 0; j < K; ++j)
+                    if (op.lpos[j] < 0 || op.lpos[j] >= a.m) return fail(QSV_E_ARG, "op target outside its tile");
+                std::vector<cd> v(D), w(D);
+                for (int g = 0; g < (T >> K); ++g) {
+                    int b = g;
+                    for (int j = 0; j < K; ++j) {
+                        const int q = op.lpos[j];
+                        b = ((b >> q) << (q + 1)) | (b & ((1 << q) - 1));
+                    }
+                    if (op.kind == OP_DENSE) {
+                        for (int r = 0; r < D; ++r) v[r] = lds[b + roff(r)];
+                        for (int r = 0; r < D; ++r) {
+                            cd acc = 0;
+                            for (int c = 0; c < D; ++c) acc += hp.pool[op.off + r * D + c] * v[c];
+                            w[r] = acc;
+                        }
+                    } else {
+                        for (int r = 0; r < D; ++r) v[r] = lds[b + roff(hp.ipool[op.ioff + r])];
+                        for (int r = 0; r < D; ++r) w[r] = op.flags ? hp.pool[op.off + r] * v[r] : v[r];
+                    }
+                    for (int r = 0; r < D; ++r) lds[b + roff(r)] = w[r];
+                }
+            }
+            for (int e = 0; e < T; ++e) st[base + off[e]] = lds[e];
+        }
+    }
+    return QSV_OK;
+}
+
 qsv_status qsv_plan_apply_range(qsv_state s, qsv_plan p, size_t first, size_t count)
 {
     qsv_status st = check_state(s);

@@ -286,7 +286,19 @@ void run_fusion(std::vector<Node>& nodes, const PlanOpts& o)
                     if (s >= 0 && s != v && pos[s] < pos[v]) ruleB = false;
                 }
                 if (!ruleA && !ruleB) continue;
-                // (2) width
+                // (2) width, checked before any product is formed
+                {
+                    unsigned long long qm = 0;
+                    for (int j = 0; j < U.g.k; ++j) qm |= 1ull << U.g.q[j];
+                    for (int j = 0; j < V.g.k; ++j) qm |= 1ull << V.g.q[j];
+                    const int kq = __builtin_popcountll(qm);
+                    if (kq > o.kmax) continue;
+                    // (5), predicted: a product with a dense factor is dense (exact
+                    // cancellation to a cheaper kind is rare and only costs a missed merge)
+                    if (o.cost_aware > 0 && (U.g.kind == OP_DENSE || V.g.kind == OP_DENSE) &&
+                        4.0 * (1 << kq) > op_fma(U.g) + op_fma(V.g) + o.sigma)
+                        continue;
+                }
                 bool ok = false;
                 FGate f = fuse_pair(U.g, V.g, o.kmax, ok);
                 if (!ok) continue;
@@ -431,7 +443,7 @@ bool make_plan(int n, int dtype, const std::vector<InGate>& gates, const PlanOpt
         PassArgs a{};
         a.m = (int)pp.active.size();
         a.L = pp.low;
-        for (int i = L; i < a.m; ++i) a.hstride[i - L] = 1ll << pp.active[i];
+        for (int i = a.L; i < a.m; ++i) a.hstride[i - a.L] = 1ll << pp.active[i];
         a.nruns = 0;
         {
             unsigned long long A = 0;

@@ -62,7 +62,7 @@ class COp(ctypes.Structure):
 EXPORTS = [
     "qsv_last_error", "qsv_version", "qsv_alloc", "qsv_free", "qsv_reset", "qsv_info", "qsv_get_state",
     "qsv_set_state", "qsv_gate_matrix", "qsv_plan_create", "qsv_plan_free", "qsv_plan_get_stats",
-    "qsv_plan_fused_gate", "qsv_plan_pass_info", "qsv_plan_pass_ops", "qsv_plan_apply", "qsv_plan_apply_range",
+    "qsv_plan_fused_gate", "qsv_plan_pass_info", "qsv_plan_pass_ops", "qsv_plan_emulate", "qsv_plan_apply", "qsv_plan_apply_range",
     "qsv_apply_fused", "qsv_sync", "qsv_norm", "qsv_expval_pauli", "qsv_probs", "qsv_adjoint_grad",
 ]
 
@@ -93,6 +93,7 @@ def lib():
     L.qsv_plan_fused_gate.argtypes = [vp, sz, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i), dp]
     L.qsv_plan_pass_info.argtypes = [vp, sz, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]
     L.qsv_plan_pass_ops.argtypes = [vp, sz, ctypes.POINTER(i)]
+    L.qsv_plan_emulate.argtypes = [vp, dp]
     L.qsv_plan_apply.argtypes = [vp, vp]
     L.qsv_plan_apply_range.argtypes = [vp, vp, sz, sz]
     L.qsv_apply_fused.argtypes = [vp, ctypes.POINTER(Gate), sz, ctypes.POINTER(PlanOpts), ctypes.POINTER(PlanStats)]
@@ -132,32 +133,51 @@ def gate_matrix(name: str, params: Sequence[float] = ()) -> np.ndarray:
     return out[: 2 * d * d].view(np.complex128).reshape(d, d).copy()
 
 
+_NAMED_CACHE = {}
+
+
+def _named(name, params):
+    key = (name, tuple(float(x) for x in params))
+    m = _NAMED_CACHE.get(key)
+    if m is None:
+        m = gate_matrix(name, params)
+        if len(_NAMED_CACHE) < 4096:
+            _NAMED_CACHE[key] = m
+    return m
+
+
 class GateList:
-    """A circuit marshalled into a ctypes qsv_gate array (owns the matrix buffers)."""
+    """A circuit marshalled into a ctypes qsv_gate array; one float64 buffer holds
+    every matrix (re, im interleaved)."""
 
     def __init__(self, ops: Iterable):
         ops = list(ops)
-        self._mats: List[np.ndarray] = []
-        self.arr = (Gate * max(1, len(ops)))()
         self.n = len(ops)
+        self.arr = (Gate * max(1, len(ops)))()
+        mats = []
+        ks = []
         for i, op in enumerate(ops):
-            if op.name == "U":
-                m = np.ascontiguousarray(op.matrix, dtype=np.complex128)
-            else:
-                m = gate_matrix(op.name, op.params)
+            m = op.matrix if op.name == "U" else _named(op.name, op.params)
             k = len(op.qubits)
             if not 1 <= k <= 5:
                 raise ValueError("op %d: a gate acts on 1 to 5 qubits, got %d" % (i, k))
             if m.shape != (1 << k, 1 << k):
                 raise ValueError("op %d: matrix shape %s does not match %d targets" % (i, m.shape, k))
-            buf = np.ascontiguousarray(m.reshape(-1)).view(np.float64).copy()
-            self._mats.append(buf)
+            mats.append(m.reshape(-1))
+            ks.append(k)
+        self._buf = np.ascontiguousarray(np.concatenate(mats) if mats else np.zeros(1, complex),
+                                         dtype=np.complex128)
+        base = self._buf.ctypes.data
+        off = 0
+        dp = ctypes.POINTER(ctypes.c_double)
+        for i, op in enumerate(ops):
             g = self.arr[i]
+            k = ks[i]
             g.k = k
-            for j, q in enumerate(op.qubits):
-                g.targets[j] = int(q)
+            g.targets[:k] = op.qubits
             g.diag = 0
-            g.mat = _dptr(buf)
+            g.mat = ctypes.cast(base + 16 * off, dp)
+            off += 1 << (2 * k)
 
 
 def _opts(fuse=True, kmax=0, cost_aware=0, tile_qubits=0, low_qubits=0, pass_budget=0.0) -> PlanOpts:
@@ -209,6 +229,12 @@ class Plan:
             idx = (ctypes.c_int * max(1, nops.value))()
             check(lib().qsv_plan_pass_ops(self.h, i, idx))
             out.append((tuple(idx[: nops.value]), tuple(act[: nact.value])))
+        return out
+
+    def emulate(self, psi: np.ndarray) -> np.ndarray:
+        """Host re-enactment of the passes (FP64) on a copy of psi (complex128)."""
+        out = np.ascontiguousarray(psi, dtype=np.complex128).copy()
+        check(lib().qsv_plan_emulate(self.h, out.view(np.float64).ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return out
 
     def free(self):

@@ -36,11 +36,11 @@ def rand_unitary(d, rng):
     return q * (np.diag(r) / np.abs(np.diag(r)))
 
 
-def check_state(got, ref, dtype):
+def check_state(got, ref, dtype, ctx=""):
     err = oracle.max_abs_diff(ref, got)
-    assert err <= TOL[dtype], "max|d alpha| = %.3g" % err
+    assert err <= TOL[dtype], "max|d alpha| = %.3g %s" % (err, ctx)
     deficit = 1.0 - oracle.fidelity(ref, got)
-    assert deficit <= DEFICIT[dtype], "fidelity deficit %.3g" % deficit
+    assert deficit <= DEFICIT[dtype], "fidelity deficit %.3g %s" % (deficit, ctx)
     return err
 
 
@@ -135,7 +135,7 @@ def test_diagonal_and_permutation_ops(qsv, dtype):
     ref = oracle.simulate(n, ops, psi=psi0.copy())
     for opts in ({}, {"fuse": False}, {"kmax": 1}, {"tile_qubits": 8, "low_qubits": 3}):
         s = run(qsv, n, dtype, ops, psi0=psi0, **opts)
-        check_state(s.get(), ref, dtype)
+        check_state(s.get(), ref, dtype, opts)
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
@@ -152,7 +152,7 @@ def test_random_multi_qubit_circuits(qsv, dtype, seed):
     for opts in ({}, {"cost_aware": -1}, {"kmax": 2}, {"fuse": False}, {"pass_budget": -1},
                  {"tile_qubits": 10, "low_qubits": 2}, {"tile_qubits": 7, "low_qubits": 6}):
         s = run(qsv, n, dtype, ops, **opts)
-        check_state(s.get(), ref, dtype)
+        check_state(s.get(), ref, dtype, opts)
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
@@ -166,7 +166,7 @@ def test_workload_circuits_20q(qsv, dtype, circuit):
     ref = oracle.simulate(n, ops)
     for opts in ({}, {"fuse": False}):
         s = run(qsv, n, dtype, ops, **opts)
-        check_state(s.get(), ref, dtype)
+        check_state(s.get(), ref, dtype, opts)
 
 
 def test_plan_reuse_and_pass_ranges(qsv):

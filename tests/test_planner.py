@@ -218,3 +218,40 @@ def test_wide_gates_in_narrow_tiles():
             assert np.max(np.abs(plan_replay(n, plan) - ref)) < 1e-12
     with pytest.raises(qsv.QSVError):
         qsv.Plan(n, "c64", ops, tile_qubits=5, low_qubits=2)
+
+
+# ------------------------------------------------------------------ device tables (host re-enactment)
+
+@pytest.mark.parametrize("seed", range(8))
+@pytest.mark.parametrize("tq,lq", [(12, 5), (12, 4), (7, 6), (6, 5), (10, 2), (6, 1), (13, 8)])
+def test_device_tables_reproduce_the_circuit(seed, tq, lq):
+    """qsv_plan_emulate walks the exact tables the pass kernel reads (tile placement,
+    strides, local bit positions, op pools); from a random state it must reproduce the
+    oracle's result for every tile geometry."""
+    rng = np.random.default_rng(1000 + seed)
+    n = 14 + seed % 3
+    ops = _random_gate_circuit(n, 40, rng)
+    ops += [C.Op("U", (int(q),), matrix=np.diag(np.exp(1j * rng.uniform(0, 6, 2)))) for q in rng.permutation(n)[:4]]
+    ops += [C.Op("CZ", (0, n - 1)), C.Op("TOFFOLI", (n - 1, 2, n - 3)), C.Op("SWAP", (1, n - 2))]
+    v = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+    psi0 = np.ascontiguousarray(v / np.linalg.norm(v))
+    ref = oracle.simulate(n, ops, psi=psi0.copy())
+    for opts in ({}, {"fuse": False}, {"cost_aware": -1}, {"kmax": 1}, {"pass_budget": -1}):
+        dt = "c64" if (seed % 2 or tq == 13) else "c128"   # 13-qubit tiles fit LDS only in complex64
+        plan = qsv.Plan(n, dt, ops, tile_qubits=tq, low_qubits=lq, **opts)
+        got = plan.emulate(psi0)
+        assert np.max(np.abs(got - ref)) < 1e-12, opts
+
+
+@pytest.mark.parametrize("circuit", ["brickwork", "hea", "qft"])
+def test_device_tables_whole_state_and_workloads(circuit):
+    for n in (9, 13, 15):
+        ops = {"brickwork": lambda: C.brickwork(n, 10, 4),
+               "hea": lambda: C.bind(C.hea(n, 3, ring=True), C.hea_params(n, 3, seed=2)),
+               "qft": lambda: C.qft(n)}[circuit]()
+        ref = oracle.simulate(n, ops)
+        psi0 = np.zeros(1 << n, complex)
+        psi0[0] = 1
+        for dt in ("c64", "c128"):
+            got = qsv.Plan(n, dt, ops).emulate(psi0)
+            assert np.max(np.abs(got - ref)) < 1e-12
