@@ -33,6 +33,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# VALU peak without packed FP32 (disabled in this build): 256 CUs x 64 FMA lanes per clock
+# x 2 flops x 2.4 GHz = 78.6 TFLOP/s, which is also MI355X's FP64 vector peak.
+VALU_PEAK_TFLOPS = 78.6
 
 
 def parse():
@@ -98,6 +101,18 @@ def run_dtype(torch, qsv, C, args, dtype, ops, terms):
     pass_bytes = 2.0 * (2 ** n) * elem
     value = st["fused_out"] * pass_bytes / sec / 1e9
     achieved = pass_bytes / (avg_pass_ms * 1e-3) / 1e9
+    # arithmetic of the average pass: the plan's FMA per amplitude (dense 4*2^k, diagonal
+    # or phased permutation 4), 2 flops each, over every amplitude
+    pass_flops = 2.0 * st["fma_per_amp"] / st["passes"] * (2 ** n)
+    alu_tflops = pass_flops / (avg_pass_ms * 1e-3) / 1e12
+    hbm_frac = achieved / HBM_PEAK_GBS
+    alu_frac = alu_tflops / VALU_PEAK_TFLOPS
+    if alu_frac > hbm_frac:
+        roof = {"bound": "alu", "achieved": alu_tflops, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": alu_frac, "traffic": None}
+    else:
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": hbm_frac, "traffic": None}
     # sanity of the result: the circuit preserves the norm
     norm = state.norm()
     out = {
@@ -109,8 +124,9 @@ def run_dtype(torch, qsv, C, args, dtype, ops, terms):
         "passes": st["passes"],
         "avg_pass_ms": avg_pass_ms,
         "norm_minus_1": norm - 1.0,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "roofline": roof,
+        "hbm": {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm_frac},
+        "alu": {"achieved": alu_tflops, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": alu_frac},
     }
     state.free()
     plan.free()
@@ -174,13 +190,15 @@ def main():
                    "fused_gates": main_rec["fused_gates"], "passes": main_rec["passes"],
                    "state": "complex64"},
         "roofline": main_rec["roofline"],
-        "detail": {k: main_rec[k] for k in ("plan_ms", "avg_pass_ms", "norm_minus_1")},
+        "hbm_frac": main_rec["hbm"]["frac"],
+        "detail": {k: main_rec[k] for k in ("plan_ms", "avg_pass_ms", "norm_minus_1", "hbm", "alu")},
     }
     if not args.no_c128:
         r = run_dtype(torch, qsv, C, args, "c128", ops, terms)
         rec["c128"] = {"value": r["value"], "unit": "GB/s", "dtype": "f64", "ms_per_step": r["ms_per_step"],
                        "fused_gates": r["fused_gates"], "passes": r["passes"], "avg_pass_ms": r["avg_pass_ms"],
-                       "roofline": r["roofline"], "norm_minus_1": r["norm_minus_1"]}
+                       "roofline": r["roofline"], "hbm": r["hbm"], "alu": r["alu"],
+                       "norm_minus_1": r["norm_minus_1"]}
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(C, args, ops)
     print(json.dumps(rec))

@@ -66,24 +66,71 @@ __device__ __forceinline__ long long local_off_bits(const PassArgs& a, int e, in
     return o;
 }
 
-// Move a tile between HBM and LDS.  Local index e = e0 + tid: the bits below 8 come
-// from the thread id (offset computed once), the bits above from the uniform loop
-// counter (offset computed in scalar registers).
+// Move a tile between HBM and LDS.  Local index e = 256 * slice + tid: the bits below 8
+// come from the thread id (offset computed once per thread), the bits above from the
+// slice number; with the slice count NS a compile-time constant every slice's offset
+// is a sum of uniform strides (scalar ALU) and all NS loads of a thread are issued
+// back to back before the first is consumed.
+__device__ __forceinline__ long long local_stride(const PassArgs& a, int i)
+{
+    return (i < a.L) ? (1ll << i) : a.hstride[i - a.L];
+}
+
+template <typename C, bool LOAD, int NS>
+__device__ __forceinline__ void move_tile_n(C* __restrict__ st, C* __restrict__ lds, const PassArgs& a,
+                                            long long toff)
+{
+    constexpr int LB = NS >= 32 ? 5 : NS >= 16 ? 4 : NS >= 8 ? 3 : NS >= 4 ? 2 : NS >= 2 ? 1 : 0;
+    long long hs[LB > 0 ? LB : 1];
+#pragma unroll
+    for (int b = 0; b < LB; ++b) hs[b] = local_stride(a, kLogThreads + b);
+    const int tid = threadIdx.x;
+    C v[NS];
+    if (LOAD) {
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            long long so = 0;
+#pragma unroll
+            for (int b = 0; b < LB; ++b)
+                if ((j >> b) & 1) so += hs[b];
+            v[j] = st[toff + so];
+        }
+#pragma unroll
+        for (int j = 0; j < NS; ++j) lds[(j << kLogThreads) + tid] = v[j];
+    } else {
+#pragma unroll
+        for (int j = 0; j < NS; ++j) v[j] = lds[(j << kLogThreads) + tid];
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            long long so = 0;
+#pragma unroll
+            for (int b = 0; b < LB; ++b)
+                if ((j >> b) & 1) so += hs[b];
+            st[toff + so] = v[j];
+        }
+    }
+}
+
 template <typename C, bool LOAD>
 __device__ __forceinline__ void move_tile(C* __restrict__ st, C* __restrict__ lds, const PassArgs& a,
                                           long long base)
 {
-    const int T = 1 << a.m;
     const int tid = threadIdx.x;
     const int lowb = a.m < kLogThreads ? a.m : kLogThreads;
     const long long toff = base + local_off_bits(a, tid, 0, lowb);
-    for (int e0 = 0; e0 < T; e0 += kThreads) {
-        const long long soff = local_off_bits(a, e0, kLogThreads, a.m);
-        const int e = e0 + tid;
-        if (e < T) {
-            if (LOAD) lds[e] = st[toff + soff];
-            else st[toff + soff] = lds[e];
+    switch (a.m - kLogThreads) {
+    case 0: move_tile_n<C, LOAD, 1>(st, lds, a, toff); break;
+    case 1: move_tile_n<C, LOAD, 2>(st, lds, a, toff); break;
+    case 2: move_tile_n<C, LOAD, 4>(st, lds, a, toff); break;
+    case 3: move_tile_n<C, LOAD, 8>(st, lds, a, toff); break;
+    case 4: move_tile_n<C, LOAD, 16>(st, lds, a, toff); break;
+    case 5: move_tile_n<C, LOAD, 32>(st, lds, a, toff); break;
+    default:   // tiles smaller than one slice (whole states below 256 amplitudes)
+        if (tid < (1 << a.m)) {
+            if (LOAD) lds[tid] = st[toff];
+            else st[toff] = lds[tid];
         }
+        break;
     }
 }
 
@@ -123,7 +170,7 @@ __device__ void op_dense(C* __restrict__ lds, int T, const DevOp& op, const C* _
         for (int r = 0; r < D; ++r) v[r] = lds[b + row_off<K>(r, op)];
         // rows are not unrolled for wide gates: the row's matrix entries are uniform
         // (scalar) loads, the inputs stay in registers
-        constexpr int RU = K <= 3 ? D : 1;
+        constexpr int RU = K <= 2 ? D : 1;
 #pragma unroll RU
         for (int r = 0; r < D; ++r) {
             C acc;

@@ -42,17 +42,19 @@ namespace qsv {
 PlanOpts default_opts(int dtype)
 {
     PlanOpts o;
+    // Budgets: measured on the 30-qubit depth-20 brickwork (the pass count / per-pass
+    // arithmetic trade-off that minimises total time).
     if (dtype == 0) {   // complex64: 8-byte amplitudes
         o.tile_qubits = 12;
         o.low_qubits = 5;
         o.whole_state_max = 13;
-        o.pass_budget = 112;
+        o.pass_budget = 224;
         o.sigma = 8;
     } else {            // complex128: 16-byte amplitudes
         o.tile_qubits = 12;
         o.low_qubits = 4;
         o.whole_state_max = 12;
-        o.pass_budget = 224;
+        o.pass_budget = 320;
         o.sigma = 8;
     }
     return o;
