@@ -225,6 +225,67 @@ qsv_status qsv_adjoint_grad(int n_qubits, qsv_dtype dtype, const qsv_op* ops, si
                             const qsv_pauli_term* H, size_t n_terms,
                             double* energy, double* grad, void* stream);
 
+/* ------------------------------------------------------------------ serving */
+
+/* Continuous-batching server.  Requests are planned on host threads, admitted FIFO while
+ * a slot is free and their HBM footprint fits (state 2^n * elem + the plan's resident
+ * matrices and tables + reduction workspace: the memory model of Eq. 14, against the
+ * device's free memory minus a reserve at creation: Eq. 15), and advanced together: each
+ * step moves every running request by its next pass(es) in one batched launch per dtype
+ * (replayed from a hipGraph), then reduces the requests that finished.  Each finished
+ * request yields its norm and per-qubit <Z_i>. */
+typedef struct qsv_server_s* qsv_server;
+
+typedef struct {
+    size_t capacity_bytes;  /* 0: free device memory at creation minus reserve_bytes */
+    size_t reserve_bytes;   /* M_reserve of Eq. 15; 0 = 1 GiB */
+    int max_slots;          /* requests running at once; 0 = 64 */
+    int passes_per_step;    /* passes each running request advances per step; 0 = 1 */
+    int grid;               /* workgroups of the persistent batched launch; 0 = 2048 */
+    int use_graph;          /* 1: capture the step's launches once and replay them */
+    int planner_threads;    /* host planning threads; 0 = 4 */
+    int keep_states;        /* 1: finished states stay on the device until qsv_server_release */
+    int dry_run;            /* 1: no device work at all (admission and scheduling only) */
+} qsv_server_opts;
+
+typedef struct {
+    long long id;
+    int n, dtype, status;   /* status: QSV_OK, QSV_E_ARG (bad circuit), QSV_E_OOM (never fits) */
+    double norm;
+    double zexp[34];        /* <Z_i>, i < n */
+    double t_submit, t_admit, t_finish;   /* seconds on the server's clock */
+    long long passes, fused;
+} qsv_result;
+
+typedef struct {
+    long long submitted, admitted, finished, rejected, steps, graph_replays, tiles, admission_waits;
+    long long peak_running, peak_used_bytes, capacity_bytes, used_bytes, running, pending;
+} qsv_server_stats;
+
+/* stream: hipStream_t for all of the server's device work (NULL: the server creates
+ * its own stream; graph capture needs a non-default stream).  Errors: QSV_E_DEVICE,
+ * QSV_E_OOM. */
+qsv_status qsv_server_create(const qsv_server_opts* opts, void* stream, qsv_server* out);
+qsv_status qsv_server_free(qsv_server s);
+
+/* Queues a request (gates copied; planning starts on a host thread).  popts may be
+ * NULL (defaults).  *id receives the request id.  Errors: QSV_E_ARG. */
+qsv_status qsv_server_submit(qsv_server s, int n_qubits, qsv_dtype dtype, const qsv_gate* gates,
+                             size_t n_gates, const qsv_plan_opts* popts, long long* id);
+
+/* Admission + one step (blocking until the step's device work is done). */
+qsv_status qsv_server_step(qsv_server s, int* n_running, int* n_pending);
+
+/* Pops up to max finished results into out (host); *count receives how many. */
+qsv_status qsv_server_results(qsv_server s, qsv_result* out, int max, int* count);
+
+qsv_status qsv_server_get_stats(qsv_server s, qsv_server_stats* st);
+
+/* keep_states only: copy a finished request's final state to host memory (2^n elements
+ * of its dtype), and release it. */
+qsv_status qsv_server_get_state(qsv_server s, long long id, void* host_out);
+qsv_status qsv_server_release(qsv_server s, long long id);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,7 +24,7 @@ from typing import List, Optional, Sequence, Tuple
 import numpy as np
 
 __all__ = [
-    "Op", "haar_u2", "brickwork", "ghz", "hea", "hea_params", "qft", "random_1q",
+    "Op", "haar_u2", "brickwork", "brickwork_arrays", "ghz", "hea", "hea_params", "qft", "random_1q",
     "tfim_terms", "zz_chain_terms", "x_sum_terms", "bind", "inverse_ops",
     "serving_stream", "Request",
 ]
@@ -70,6 +70,28 @@ def brickwork(n: int, depth: int, seed: int) -> List[Op]:
         for c in range(start, n - 1, 2):
             ops.append(Op("CNOT", (c, c + 1)))
     return ops
+
+
+def brickwork_arrays(n: int, depth: int, seed: int):
+    """The circuit of ``brickwork(n, depth, seed)`` as arrays (same draws, same order), for
+    marshalling many circuits quickly: ``code`` per gate (0 = raw unitary, 1 = CNOT),
+    ``targets`` (gates x 2, -1 padded), ``k`` (1 or 2), and the raw unitaries in order
+    (u x 2 x 2 complex128)."""
+    rng = np.random.default_rng(seed)
+    codes, ks, tg, mats = [], [], [], []
+    for layer in range(depth):
+        mats.append(haar_u2(rng, n))
+        codes += [0] * n
+        ks += [1] * n
+        tg += [(q, -1) for q in range(n)]
+        start = layer % 2
+        for c in range(start, n - 1, 2):
+            codes.append(1)
+            ks.append(2)
+            tg.append((c, c + 1))
+    return {"code": np.array(codes, dtype=np.int8), "k": np.array(ks, dtype=np.int32),
+            "targets": np.array(tg, dtype=np.int32).reshape(-1, 2),
+            "unitaries": np.concatenate(mats) if mats else np.zeros((0, 2, 2), complex)}
 
 
 def ghz(n: int) -> List[Op]:

@@ -49,6 +49,10 @@ struct DeviceGuard {
 
 }  // namespace
 
+namespace qsv {
+qsv_status set_error(qsv_status st, const std::string& msg) { return fail(st, msg); }
+}  // namespace qsv
+
 struct qsv_state_s {
     int n = 0;
     int dtype = 0;
@@ -145,6 +149,14 @@ bool read_gate(const qsv_gate& g, int n, InGate& out, std::string& err)
         if (!std::isfinite(v.real()) || !std::isfinite(v.imag())) { err = "non-finite gate matrix entry"; return false; }
     return true;
 }
+
+}  // namespace
+
+namespace qsv {
+bool read_gate_public(const qsv_gate& g, int n, InGate& out, std::string& err) { return read_gate(g, n, out, err); }
+}  // namespace qsv
+
+namespace {
 
 qsv_status upload_plan(qsv_plan p, int device)
 {

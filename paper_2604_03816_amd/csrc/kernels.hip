@@ -252,6 +252,19 @@ __device__ void apply_ops(C* __restrict__ lds, int T, const DevOp* __restrict__ 
     }
 }
 
+// One tile of one pass: HBM -> LDS, every op of the pass, LDS -> HBM.
+template <typename C>
+__device__ __forceinline__ void run_tile(C* __restrict__ st, C* __restrict__ lds, const PassArgs& a, long long tile,
+                                         const DevOp* __restrict__ ops, const C* __restrict__ pool,
+                                         const int* __restrict__ ipool)
+{
+    const long long base = tile_base(a, tile);
+    move_tile<C, true>(st, lds, a, base);
+    __syncthreads();
+    apply_ops<C>(lds, 1 << a.m, ops, a.op_begin, a.op_count, pool, ipool, base);
+    move_tile<C, false>(st, lds, a, base);
+}
+
 template <typename C>
 __global__ __launch_bounds__(kThreads) void k_pass(C* __restrict__ st, const PassArgs a,
                                                    const DevOp* __restrict__ ops,
@@ -260,11 +273,34 @@ __global__ __launch_bounds__(kThreads) void k_pass(C* __restrict__ st, const Pas
 {
     extern __shared__ __align__(16) unsigned char smem[];
     C* lds = reinterpret_cast<C*>(smem);
-    const long long base = tile_base(a, blockIdx.x);
-    move_tile<C, true>(st, lds, a, base);
-    __syncthreads();
-    apply_ops<C>(lds, 1 << a.m, ops, a.op_begin, a.op_count, pool, ipool, base);
-    move_tile<C, false>(st, lds, a, base);
+    run_tile<C>(st, lds, a, blockIdx.x, ops, pool, ipool);
+}
+
+// Batched pass for continuous batching: one launch advances many independent states,
+// each by its own current pass.  Work item w (a tile of one item's pass) is found by
+// binary search over the items' tile prefix sums; the grid is persistent (fixed size,
+// strided over the work list) so the launch can be captured once and replayed.
+template <typename C>
+__global__ __launch_bounds__(kThreads) void k_batch_pass(const BatchItem* __restrict__ items,
+                                                         const int* __restrict__ count)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    C* lds = reinterpret_cast<C*>(smem);
+    const int nitems = *count;
+    if (nitems <= 0) return;
+    const long long total = items[nitems - 1].tile_end;
+    for (long long w = blockIdx.x; w < total; w += gridDim.x) {
+        int lo = 0, hi = nitems - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (items[mid].tile_end <= w) lo = mid + 1;
+            else hi = mid;
+        }
+        const BatchItem& it = items[lo];
+        const long long tile = w - (it.tile_end - it.ntiles);
+        run_tile<C>((C*)it.state, lds, it.a, tile, it.ops, (const C*)it.pool, it.ipool);
+        __syncthreads();   // the next work item reuses the LDS tile
+    }
 }
 
 template <typename C>
@@ -499,7 +535,66 @@ __global__ __launch_bounds__(kThreads) void k_sum_chunks(const double* __restric
     out[o] = s.s + s.c;
 }
 
+// Per-qubit <Z_i> and norm of finished served states, batched: work item = one chunk of
+// 2^12 consecutive amplitudes of one state.  Each workgroup writes, for its chunk, the
+// chunk's sum of |alpha|^2 and, for the qubits inside the chunk (bits < 12), the sum
+// over amplitudes with that bit set; qubits >= 12 are constant over a chunk and are
+// resolved on the host from the chunk sum.  Fixed partition and reduction order.
+constexpr int kZChunkQubits = 12;
+
+template <typename C>
+__global__ __launch_bounds__(kThreads) void k_zsum_batch(const ZItem* __restrict__ items, const int* __restrict__ count,
+                                                         double* __restrict__ partial)
+{
+    __shared__ NSum scratch[kThreads / 64];
+    const int nitems = *count;
+    if (nitems <= 0) return;
+    const long long total = items[nitems - 1].chunk_end;
+    for (long long w = blockIdx.x; w < total; w += gridDim.x) {
+        int lo = 0, hi = nitems - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (items[mid].chunk_end <= w) lo = mid + 1;
+            else hi = mid;
+        }
+        const ZItem& it = items[lo];
+        const long long chunk = w - (it.chunk_end - it.nchunks);
+        const int cq = it.n < kZChunkQubits ? it.n : kZChunkQubits;
+        const int len = 1 << cq;
+        const C* st = (const C*)it.state + (chunk << cq);
+        double tot = 0.0, bits[kZChunkQubits];
+#pragma unroll
+        for (int b = 0; b < kZChunkQubits; ++b) bits[b] = 0.0;
+        for (int e = threadIdx.x; e < len; e += kThreads) {
+            const C v = st[e];
+            const double p = (double)v.x * v.x + (double)v.y * v.y;
+            tot += p;
+#pragma unroll
+            for (int b = 0; b < kZChunkQubits; ++b)
+                if ((e >> b) & 1) bits[b] += p;
+        }
+        double* out = partial + (it.partial_off + chunk * (kZChunkQubits + 1));
+        NSum r = block_reduce(NSum{tot, 0.0}, scratch);
+        if (threadIdx.x == 0) out[0] = r.s + r.c;
+#pragma unroll
+        for (int b = 0; b < kZChunkQubits; ++b) {
+            r = block_reduce(NSum{bits[b], 0.0}, scratch);
+            if (threadIdx.x == 0) out[1 + b] = r.s + r.c;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ launchers
+
+hipError_t launch_zsum_batch(int dtype, const ZItem* items, const int* count, double* partial, int grid,
+                             hipStream_t s)
+{
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_zsum_batch<float2>, dim3(grid), dim3(kThreads), 0, s, items, count, partial);
+    else
+        hipLaunchKernelGGL(k_zsum_batch<double2>, dim3(grid), dim3(kThreads), 0, s, items, count, partial);
+    return hipGetLastError();
+}
 
 template <typename R>
 hipError_t launch_pass_t(void* st, const PassArgs& a, long long grid, const DevOp* ops, const void* pool,
@@ -515,6 +610,31 @@ hipError_t launch_pass_t(void* st, const PassArgs& a, long long grid, const DevO
     }
     hipLaunchKernelGGL(k_pass<C>, dim3((unsigned)grid), dim3(kThreads), lds, s, (C*)st, a, ops,
                        (const C*)pool, ipool);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_pass(int dtype, const BatchItem* items, const int* count, int grid, hipStream_t s)
+{
+    const size_t lds = (dtype == 0 ? sizeof(float2) : sizeof(double2)) << kMaxTileQubitsC(dtype);
+    if (dtype == 0) {
+        static bool set = false;
+        if (!set) {
+            hipError_t e = hipFuncSetAttribute((const void*)k_batch_pass<float2>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+            if (e != hipSuccess) return e;
+            set = true;
+        }
+        hipLaunchKernelGGL(k_batch_pass<float2>, dim3(grid), dim3(kThreads), lds, s, items, count);
+    } else {
+        static bool set = false;
+        if (!set) {
+            hipError_t e = hipFuncSetAttribute((const void*)k_batch_pass<double2>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+            if (e != hipSuccess) return e;
+            set = true;
+        }
+        hipLaunchKernelGGL(k_batch_pass<double2>, dim3(grid), dim3(kThreads), lds, s, items, count);
+    }
     return hipGetLastError();
 }
 

@@ -75,7 +75,34 @@ struct MargArgs {
     long long nchunks;
 };
 
+// One state's current pass inside a batched launch (continuous batching).
+struct BatchItem {
+    void* state;
+    const DevOp* ops;
+    const void* pool;
+    const int* ipool;
+    long long ntiles;     // tiles of this pass
+    long long tile_end;   // prefix sum of ntiles over the items up to and including this one
+    PassArgs a;
+};
+
+// A finished served state whose <Z_i> and norm are reduced in a batched launch.
+struct ZItem {
+    const void* state;
+    int n;
+    int pad;
+    long long nchunks;      // 2^max(0, n - 12) chunks of 2^min(n, 12) amplitudes
+    long long chunk_end;    // prefix sum of nchunks
+    long long partial_off;  // first double of this state's partials (13 per chunk)
+};
+
+// Largest tile (log2 amplitudes) a dtype's pass kernel holds in LDS (64 KiB).
+__host__ __device__ constexpr int kMaxTileQubitsC(int dt) { return dt == 0 ? 13 : 12; }
+
 // Launchers (kernels.hip).  dtype 0 = complex64, 1 = complex128.
+hipError_t launch_batch_pass(int dtype, const BatchItem* items, const int* count, int grid, hipStream_t s);
+hipError_t launch_zsum_batch(int dtype, const ZItem* items, const int* count, double* partial, int grid,
+                             hipStream_t s);
 hipError_t launch_pass(int dtype, void* st, const PassArgs& a, long long grid, const DevOp* ops,
                        const void* pool, const int* ipool, hipStream_t s);
 hipError_t launch_init_zero(int dtype, void* st, long long N, hipStream_t s);

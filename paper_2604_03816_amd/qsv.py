@@ -64,6 +64,8 @@ EXPORTS = [
     "qsv_set_state", "qsv_gate_matrix", "qsv_plan_create", "qsv_plan_free", "qsv_plan_get_stats",
     "qsv_plan_fused_gate", "qsv_plan_pass_info", "qsv_plan_pass_ops", "qsv_plan_emulate", "qsv_plan_apply", "qsv_plan_apply_range",
     "qsv_apply_fused", "qsv_sync", "qsv_norm", "qsv_expval_pauli", "qsv_probs", "qsv_adjoint_grad",
+    "qsv_server_create", "qsv_server_free", "qsv_server_submit", "qsv_server_step", "qsv_server_results",
+    "qsv_server_get_stats", "qsv_server_get_state", "qsv_server_release",
 ]
 
 _LIB = None
@@ -180,6 +182,38 @@ class GateList:
             off += 1 << (2 * k)
 
 
+_GATE_DTYPE = np.dtype({"names": ["k", "targets", "diag", "mat"],
+                        "formats": ["<i4", ("<i4", (5,)), "<i4", "<u8"],
+                        "offsets": [0, 4, 24, 32], "itemsize": 40})
+assert _GATE_DTYPE.itemsize == ctypes.sizeof(Gate)
+
+
+class ArrayGateList:
+    """A circuit given as arrays (see circuits.brickwork_arrays) marshalled into qsv_gate
+    structs with numpy, without a Python loop over gates.  code 0 = raw unitary (taken
+    in order from ``unitaries``), code 1 = CNOT (the library's Eq. 4 matrix)."""
+
+    def __init__(self, arr):
+        code, k, tg, us = arr["code"], arr["k"], arr["targets"], arr["unitaries"]
+        G = len(code)
+        self.n = G
+        cnot = gate_matrix("CNOT").reshape(-1)
+        self._buf = np.ascontiguousarray(np.concatenate([us.reshape(-1), cnot]), dtype=np.complex128)
+        base = self._buf.ctypes.data
+        cnot_addr = base + 16 * 4 * len(us)
+        a = np.zeros(max(1, G), dtype=_GATE_DTYPE)
+        a["k"][:G] = k
+        t = np.zeros((max(1, G), 5), dtype=np.int32)
+        t[:G, :2] = tg
+        t[:G, 1][k == 1] = 0
+        a["targets"] = t
+        uidx = np.cumsum(code == 0) - 1
+        addr = np.where(code == 0, base + 64 * uidx, cnot_addr).astype(np.uint64)
+        a["mat"][:G] = addr
+        self._arr = a
+        self.arr = a.ctypes.data_as(ctypes.POINTER(Gate))
+
+
 def _opts(fuse=True, kmax=0, cost_aware=0, tile_qubits=0, low_qubits=0, pass_budget=0.0) -> PlanOpts:
     o = PlanOpts()
     o.fuse = 1 if fuse else 0
@@ -197,7 +231,7 @@ class Plan:
     def __init__(self, n: int, dtype: str, ops: Iterable, **opts):
         self.n = n
         self.dtype = dtype
-        gl = ops if isinstance(ops, GateList) else GateList(ops)
+        gl = ops if isinstance(ops, (GateList, ArrayGateList)) else GateList(ops)
         h = ctypes.c_void_p()
         o = _opts(**opts)
         check(lib().qsv_plan_create(n, _DT[dtype], gl.arr, gl.n, ctypes.byref(o), ctypes.byref(h)))
@@ -293,7 +327,7 @@ class State:
 
     # -- application
     def apply(self, ops, **opts) -> dict:
-        gl = ops if isinstance(ops, GateList) else GateList(ops)
+        gl = ops if isinstance(ops, (GateList, ArrayGateList)) else GateList(ops)
         st = PlanStats()
         o = _opts(**opts)
         check(lib().qsv_apply_fused(self.h, gl.arr, gl.n, ctypes.byref(o), ctypes.byref(st)))

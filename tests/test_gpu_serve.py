@@ -1,0 +1,140 @@
+"""Serving on the GPU: every served result matches the FP64 oracle, a request's final
+state and results are identical alone and in a mix of concurrently running requests
+(continuous batching changes nothing per request), graph replay equals direct launches,
+and admission under a small HBM capacity still completes every request."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_03816_amd import circuits as C
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mods():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2604_03816_amd import qsv, serve
+    qsv.lib()
+    return qsv, serve
+
+
+def drain(sv):
+    out = []
+    for _ in range(100000):
+        r, p = sv.step()
+        out += sv.results()
+        st = sv.stats()
+        if r == 0 and p == 0 and st["finished"] + st["rejected"] >= st["submitted"]:
+            return out + sv.results()
+    raise AssertionError("server did not drain")
+
+
+def zexp_oracle(n, ops):
+    psi = oracle.simulate(n, ops)
+    return np.array([oracle.pauli_expval(psi, ((q, "Z"),)).real for q in range(n)]), oracle.norm2(psi), psi
+
+
+def mix(seed, count=24):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for _ in range(count):
+        n = int(rng.integers(6, 17))
+        reqs.append((n, "c64" if rng.random() < 0.6 else "c128", C.brickwork(n, int(rng.integers(2, 9)), int(rng.integers(1 << 30)))))
+    return reqs
+
+
+def test_served_results_match_oracle(mods):
+    qsv, serve = mods
+    sv = serve.Server(max_slots=16)
+    reqs = mix(1)
+    ids = {sv.submit(n, dt, ops): (n, dt, ops) for n, dt, ops in reqs}
+    res = drain(sv)
+    assert len(res) == len(reqs)
+    for r in res:
+        n, dt, ops = ids[r["id"]]
+        z, nrm, _ = zexp_oracle(n, ops)
+        tol = 1e-12 if dt == "c128" else 5e-5
+        assert r["status"] == 0
+        assert abs(r["norm"] - nrm) <= tol
+        assert np.max(np.abs(r["zexp"] - z)) <= tol, (n, dt)
+    sv.close()
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_alone_versus_in_the_mix(mods, dtype):
+    qsv, serve = mods
+    n = 15
+    probe = C.brickwork(n, 12, 77)
+    alone = serve.Server(max_slots=8, keep_states=True)
+    pid = alone.submit(n, dtype, probe)
+    ra = [r for r in drain(alone) if r["id"] == pid][0]
+    sa = alone.get_state(pid, n, dtype)
+    alone.close()
+    # in a mix: other requests before, with and after the probe
+    sv = serve.Server(max_slots=8, keep_states=True)
+    others = mix(2, 20)
+    for n2, dt2, ops2 in others[:10]:
+        sv.submit(n2, dt2, ops2)
+    sv.step()
+    qid = sv.submit(n, dtype, probe)
+    for n2, dt2, ops2 in others[10:]:
+        sv.submit(n2, dt2, ops2)
+    rm = [r for r in drain(sv) if r["id"] == qid][0]
+    sm = sv.get_state(qid, n, dtype)
+    assert sv.stats()["peak_running"] > 1
+    assert np.array_equal(sa, sm), "final state differs between alone and in the mix"
+    assert ra["norm"] == rm["norm"] and np.array_equal(ra["zexp"], rm["zexp"])
+    # and equal to the plain path's state within tolerance (same circuit, one at a time)
+    s = qsv.State(n, dtype)
+    s.apply(probe)
+    tol = 1e-12 if dtype == "c128" else 5e-6
+    assert np.max(np.abs(s.get().astype(np.complex128) - sm.astype(np.complex128))) <= tol
+    _, _, psi = zexp_oracle(n, probe)
+    assert np.max(np.abs(psi - sm.astype(np.complex128))) <= tol
+    sv.close()
+
+
+def test_graph_replay_equals_direct_launches(mods):
+    qsv, serve = mods
+    reqs = mix(3, 16)
+    outs = []
+    for use_graph in (True, False):
+        sv = serve.Server(max_slots=6, use_graph=use_graph, passes_per_step=2)
+        ids = [sv.submit(n, dt, ops) for n, dt, ops in reqs]
+        res = {r["id"]: r for r in drain(sv)}
+        outs.append([(res[i]["norm"], tuple(res[i]["zexp"])) for i in ids])
+        if use_graph:
+            assert sv.stats()["graph_replays"] >= 2
+        sv.close()
+    assert outs[0] == outs[1]
+
+
+def test_small_capacity_admission_on_device(mods):
+    qsv, serve = mods
+    reqs = mix(4, 12)
+    cap = max((1 << n) * (8 if dt == "c64" else 16) for n, dt, _ in reqs) * 3 // 2 + (1 << 20)
+    sv = serve.Server(max_slots=8, capacity_bytes=cap)
+    ids = {sv.submit(n, dt, ops): (n, dt, ops) for n, dt, ops in reqs}
+    res = drain(sv)
+    st = sv.stats()
+    assert st["finished"] == len(reqs)
+    assert st["peak_used_bytes"] <= cap
+    for r in res:
+        n, dt, ops = ids[r["id"]]
+        z, _, _ = zexp_oracle(n, ops)
+        assert np.max(np.abs(r["zexp"] - z)) <= (1e-12 if dt == "c128" else 5e-5)
+    sv.close()
+
+
+def test_open_loop_stream_and_plain_path(mods):
+    qsv, serve = mods
+    reqs = C.serving_stream(40, seed=9, rate_hz=400.0, n_lo=12, n_hi=18, d_lo=5, d_hi=15)
+    circuits = [qsv.ArrayGateList(C.brickwork_arrays(r.n, r.depth, r.seed)) for r in reqs]
+    sv = serve.Server(max_slots=32)
+    out = serve.run_batched(reqs, circuits, sv)
+    assert out["completed"] == 40 and out["p99_ms"] >= out["p50_ms"] > 0
+    sv.close()
+    plain = serve.run_plain(reqs[:8], circuits[:8])
+    assert plain["completed"] == 8
