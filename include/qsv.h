@@ -123,6 +123,7 @@ typedef struct {
     size_t fused_out;      /* fused gates after DAG fusion */
     size_t passes;         /* HBM passes (kernel launches) per application */
     size_t dense_ops, diag_ops, perm_ops;
+    size_t mfma_ops;       /* dense complex64 ops run on FP32 matrix cores */
     double fma_per_amp;    /* complex-arithmetic cost summed over all passes */
     double hbm_bytes;      /* algorithmic HBM bytes per application = passes * 2 * 2^n * elem */
 } qsv_plan_stats;
@@ -239,7 +240,7 @@ typedef struct qsv_server_s* qsv_server;
 typedef struct {
     size_t capacity_bytes;  /* 0: free device memory at creation minus reserve_bytes */
     size_t reserve_bytes;   /* M_reserve of Eq. 15; 0 = 1 GiB */
-    int max_slots;          /* requests running at once; 0 = 64 */
+    int max_slots;          /* requests running at once; 0 = 64, at most 256 */
     int passes_per_step;    /* passes each running request advances per step; 0 = 1 */
     int grid;               /* workgroups of the persistent batched launch; 0 = 2048 */
     int use_graph;          /* 1: capture the step's launches once and replay them */

@@ -253,14 +253,14 @@ PassArgs tile_args(int n, int m, int L, unsigned long long need, std::vector<int
     PassArgs a{};
     a.m = (int)active.size();
     a.L = std::min(L, a.m);
-    for (int i = a.L; i < a.m; ++i) a.hstride[i - a.L] = 1ll << active[i];
+    for (int i = a.L; i < a.m; ++i) a.hbit[i - a.L] = (unsigned char)active[i];
     int b = 0;
     while (b < n) {
         if ((A >> b) & 1) { ++b; continue; }
         const int s = b;
         while (b < n && !((A >> b) & 1)) ++b;
-        a.run_pos[a.nruns] = s;
-        a.run_len[a.nruns] = b - s;
+        a.run_pos[a.nruns] = (unsigned char)s;
+        a.run_len[a.nruns] = (unsigned char)(b - s);
         ++a.nruns;
     }
     return a;
@@ -607,6 +607,7 @@ qsv_status qsv_plan_get_stats(qsv_plan p, qsv_plan_stats* st)
     st->dense_ops = hp.dense_ops;
     st->diag_ops = hp.diag_ops;
     st->perm_ops = hp.perm_ops;
+    st->mfma_ops = hp.mfma_ops;
     st->fma_per_amp = hp.fma_per_amp;
     st->hbm_bytes = (double)hp.passes.size() * 2.0 * (double)(elem_bytes(hp.dtype) << hp.n);
     return QSV_OK;
@@ -664,7 +665,7 @@ qsv_status qsv_plan_emulate(qsv_plan p, double* state)
         for (int e = 0; e < T; ++e) {
             long long o = 0;
             for (int i = 0; i < a.m; ++i)
-                if ((e >> i) & 1) o += (i < a.L) ? (1ll << i) : a.hstride[i - a.L];
+                if ((e >> i) & 1) o += (i < a.L) ? (1ll << i) : (1ll << a.hbit[i - a.L]);
             off[e] = o;
         }
         for (long long t = 0; t < hp.pgrid[pi]; ++t) {

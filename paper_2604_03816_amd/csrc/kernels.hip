@@ -19,10 +19,25 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "qsv_internal.h"
 
 namespace qsv {
+
+// Address-space-qualified pointers: the state lives in global memory, plan tables are
+// read-only (constant address space, so uniform reads become scalar loads).  Pointers
+// that a kernel reads from memory (batched launches) carry no address space of their
+// own; typing the helpers' parameters keeps every access global or scalar, never flat.
+// (The host compilation pass of this file never runs these helpers and sees plain
+// pointers.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T> using gptr = __attribute__((address_space(1))) T*;
+template <typename T> using cptr = const __attribute__((address_space(4))) T*;
+#else
+template <typename T> using gptr = T*;
+template <typename T> using cptr = const T*;
+#endif
 
 template <typename R> struct CT;
 template <> struct CT<float> { using T = float2; };
@@ -61,7 +76,7 @@ __device__ __forceinline__ long long local_off_bits(const PassArgs& a, int e, in
 {
     long long o = 0;
     for (int i = lo; i < hi; ++i) {
-        if ((e >> i) & 1) o += (i < a.L) ? (1ll << i) : a.hstride[i - a.L];
+        if ((e >> i) & 1) o += (i < a.L) ? (1ll << i) : (1ll << a.hbit[i - a.L]);
     }
     return o;
 }
@@ -73,11 +88,11 @@ __device__ __forceinline__ long long local_off_bits(const PassArgs& a, int e, in
 // back to back before the first is consumed.
 __device__ __forceinline__ long long local_stride(const PassArgs& a, int i)
 {
-    return (i < a.L) ? (1ll << i) : a.hstride[i - a.L];
+    return (i < a.L) ? (1ll << i) : (1ll << a.hbit[i - a.L]);
 }
 
 template <typename C, bool LOAD, int NS>
-__device__ __forceinline__ void move_tile_n(C* __restrict__ st, C* __restrict__ lds, const PassArgs& a,
+__device__ __forceinline__ void move_tile_n(gptr<C> __restrict__ st, C* __restrict__ lds, const PassArgs& a,
                                             long long toff)
 {
     constexpr int LB = NS >= 32 ? 5 : NS >= 16 ? 4 : NS >= 8 ? 3 : NS >= 4 ? 2 : NS >= 2 ? 1 : 0;
@@ -112,7 +127,7 @@ __device__ __forceinline__ void move_tile_n(C* __restrict__ st, C* __restrict__ 
 }
 
 template <typename C, bool LOAD>
-__device__ __forceinline__ void move_tile(C* __restrict__ st, C* __restrict__ lds, const PassArgs& a,
+__device__ __forceinline__ void move_tile(gptr<C> __restrict__ st, C* __restrict__ lds, const PassArgs& a,
                                           long long base)
 {
     const int tid = threadIdx.x;
@@ -159,7 +174,7 @@ __device__ __forceinline__ int group_base(int g, const DevOp& op)
 }
 
 template <typename C, int K>
-__device__ void op_dense(C* __restrict__ lds, int T, const DevOp& op, const C* __restrict__ M)
+__device__ void op_dense(C* __restrict__ lds, int T, const DevOp& op, cptr<C> __restrict__ M)
 {
     constexpr int D = 1 << K;
     const int G = T >> K;
@@ -183,9 +198,53 @@ __device__ void op_dense(C* __restrict__ lds, int T, const DevOp& op, const C* _
     }
 }
 
+// Dense complex64 op on FP32 matrix cores.  The op is the real-embedded 2D x 2D matrix
+// (D = 2^K) times the tile viewed as D x (T / D) complex columns (one column per group of
+// amplitudes that differ only in the op's targets).  A wave takes 16 groups at a time:
+// lane (q, col) = (lane / 16, lane % 16) feeds group `col`, complex input rows 4 j + q
+// (real part, then imaginary part, as two K = 4 steps), and receives output rows
+// 8 rb + 2 q and 8 rb + 2 q + 1 of row block rb.  The A operands (host-arranged, see
+// the planner) stay in registers for the whole op.  All reads of a block precede its
+// writes, so the update is in place; waves own disjoint groups.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+template <int K>
+__device__ void op_dense_mfma(float2* __restrict__ lds, int T, const DevOp& op, cptr<float> __restrict__ A)
+{
+    constexpr int D = 1 << K, R2 = 2 * D, RB = R2 / 16, KS = R2 / 4;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int q = lane >> 4, col = lane & 15;
+    float a[RB][KS];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) a[rb][ks] = A[(rb * KS + ks) * 64 + lane];
+    const int nblk = (T >> K) >> 4;
+    for (int blk = wave; blk < nblk; blk += kThreads / 64) {
+        const int b = group_base<K>((blk << 4) + col, op);
+        floatx4 acc[RB];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) acc[rb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int j = 0; j < KS / 2; ++j) {
+            const float2 v = lds[b + row_off<K>(4 * j + q, op)];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][2 * j], v.x, acc[rb], 0, 0, 0);
+                acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][2 * j + 1], v.y, acc[rb], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+            lds[b + row_off<K>(8 * rb + 2 * q, op)] = make_float2(acc[rb][0], acc[rb][1]);
+            lds[b + row_off<K>(8 * rb + 2 * q + 1, op)] = make_float2(acc[rb][2], acc[rb][3]);
+        }
+    }
+}
+
 template <typename C, int K>
-__device__ void op_perm(C* __restrict__ lds, int T, const DevOp& op, const C* __restrict__ ph,
-                        const int* __restrict__ src)
+__device__ void op_perm(C* __restrict__ lds, int T, const DevOp& op, cptr<C> __restrict__ ph,
+                        cptr<int> __restrict__ src)
 {
     constexpr int D = 1 << K;
     const int G = T >> K;
@@ -201,7 +260,7 @@ __device__ void op_perm(C* __restrict__ lds, int T, const DevOp& op, const C* __
 }
 
 template <typename C>
-__device__ void op_diag(C* __restrict__ lds, int T, const DevOp& op, const C* __restrict__ Dg,
+__device__ void op_diag(C* __restrict__ lds, int T, const DevOp& op, cptr<C> __restrict__ Dg,
                         long long base)
 {
     // targets outside the tile contribute a per-tile constant part of the table index
@@ -221,13 +280,25 @@ __device__ void op_diag(C* __restrict__ lds, int T, const DevOp& op, const C* __
 }
 
 template <typename C>
-__device__ void apply_ops(C* __restrict__ lds, int T, const DevOp* __restrict__ ops, int op_begin,
-                          int op_count, const C* __restrict__ pool, const int* __restrict__ ipool,
+__device__ void apply_ops(C* __restrict__ lds, int T, cptr<DevOp> __restrict__ ops, int op_begin,
+                          int op_count, cptr<C> __restrict__ pool, cptr<int> __restrict__ ipool,
                           long long base)
 {
     for (int oi = 0; oi < op_count; ++oi) {
         const DevOp op = ops[op_begin + oi];
-        const C* M = pool + op.off;
+        cptr<C> M = pool + op.off;
+        if constexpr (std::is_same<C, float2>::value) {
+            if (op.kind == OP_DENSE && op.aoff >= 0 && ((T >> op.k) >> 4) > 0) {
+                cptr<float> Am = (cptr<float>)(pool + op.aoff);
+                switch (op.k) {
+                case 3: op_dense_mfma<3>(lds, T, op, Am); break;
+                case 4: op_dense_mfma<4>(lds, T, op, Am); break;
+                default: op_dense_mfma<5>(lds, T, op, Am); break;
+                }
+                __syncthreads();
+                continue;
+            }
+        }
         if (op.kind == OP_DENSE) {
             switch (op.k) {
             case 1: op_dense<C, 1>(lds, T, op, M); break;
@@ -237,7 +308,7 @@ __device__ void apply_ops(C* __restrict__ lds, int T, const DevOp* __restrict__ 
             default: op_dense<C, 5>(lds, T, op, M); break;
             }
         } else if (op.kind == OP_PERM) {
-            const int* S = ipool + op.ioff;
+            cptr<int> S = ipool + op.ioff;
             switch (op.k) {
             case 1: op_perm<C, 1>(lds, T, op, M, S); break;
             case 2: op_perm<C, 2>(lds, T, op, M, S); break;
@@ -254,9 +325,9 @@ __device__ void apply_ops(C* __restrict__ lds, int T, const DevOp* __restrict__ 
 
 // One tile of one pass: HBM -> LDS, every op of the pass, LDS -> HBM.
 template <typename C>
-__device__ __forceinline__ void run_tile(C* __restrict__ st, C* __restrict__ lds, const PassArgs& a, long long tile,
-                                         const DevOp* __restrict__ ops, const C* __restrict__ pool,
-                                         const int* __restrict__ ipool)
+__device__ __forceinline__ void run_tile(gptr<C> __restrict__ st, C* __restrict__ lds, const PassArgs& a,
+                                         long long tile, cptr<DevOp> __restrict__ ops, cptr<C> __restrict__ pool,
+                                         cptr<int> __restrict__ ipool)
 {
     const long long base = tile_base(a, tile);
     move_tile<C, true>(st, lds, a, base);
@@ -273,7 +344,7 @@ __global__ __launch_bounds__(kThreads) void k_pass(C* __restrict__ st, const Pas
 {
     extern __shared__ __align__(16) unsigned char smem[];
     C* lds = reinterpret_cast<C*>(smem);
-    run_tile<C>(st, lds, a, blockIdx.x, ops, pool, ipool);
+    run_tile<C>((gptr<C>)st, lds, a, blockIdx.x, (cptr<DevOp>)ops, (cptr<C>)pool, (cptr<int>)ipool);
 }
 
 // Batched pass for continuous batching: one launch advances many independent states,
@@ -286,19 +357,29 @@ __global__ __launch_bounds__(kThreads) void k_batch_pass(const BatchItem* __rest
 {
     extern __shared__ __align__(16) unsigned char smem[];
     C* lds = reinterpret_cast<C*>(smem);
-    const int nitems = *count;
+    __shared__ long long ends[kMaxBatchItems];
+    const int nitems = min(*count, kMaxBatchItems);
     if (nitems <= 0) return;
-    const long long total = items[nitems - 1].tile_end;
+    for (int i = threadIdx.x; i < nitems; i += kThreads) ends[i] = items[i].tile_end;
+    __syncthreads();
+    const long long total = ends[nitems - 1];
     for (long long w = blockIdx.x; w < total; w += gridDim.x) {
         int lo = 0, hi = nitems - 1;
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
-            if (items[mid].tile_end <= w) lo = mid + 1;
+            if (ends[mid] <= w) lo = mid + 1;
             else hi = mid;
         }
+        // the search runs on LDS values, which live in vector registers; the result is
+        // the same on every lane, and saying so keeps every later descriptor and op
+        // table read a scalar (uniform) load
+        lo = __builtin_amdgcn_readfirstlane(lo);
         const BatchItem& it = items[lo];
         const long long tile = w - (it.tile_end - it.ntiles);
-        run_tile<C>((C*)it.state, lds, it.a, tile, it.ops, (const C*)it.pool, it.ipool);
+        // pointers read from memory carry no address space: state in global memory
+        // (global, not flat, loads and stores), plan tables read-only (scalar loads)
+        run_tile<C>((gptr<C>)it.state, lds, it.a, tile, (cptr<DevOp>)it.ops, (cptr<C>)it.pool,
+                    (cptr<int>)it.ipool);
         __syncthreads();   // the next work item reuses the LDS tile
     }
 }
@@ -412,7 +493,7 @@ __global__ __launch_bounds__(kThreads) void k_expval(const C* __restrict__ sa, c
     for (int i = 0; i < kMaxTermsPerLaunch; ++i) acc[i] = 0.0;
     for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const long long base = tile_base(a, tile);
-        move_tile<C, true>(const_cast<C*>(sa), lds, a, base);
+        move_tile<C, true>((gptr<C>)const_cast<C*>(sa), lds, a, base);
         __syncthreads();
         int gpar[kMaxTermsPerLaunch];
 #pragma unroll
@@ -613,9 +694,10 @@ hipError_t launch_pass_t(void* st, const PassArgs& a, long long grid, const DevO
     return hipGetLastError();
 }
 
-hipError_t launch_batch_pass(int dtype, const BatchItem* items, const int* count, int grid, hipStream_t s)
+hipError_t launch_batch_pass(int dtype, const BatchItem* items, const int* count, int grid, int tile_qubits,
+                             hipStream_t s)
 {
-    const size_t lds = (dtype == 0 ? sizeof(float2) : sizeof(double2)) << kMaxTileQubitsC(dtype);
+    const size_t lds = (dtype == 0 ? sizeof(float2) : sizeof(double2)) << tile_qubits;
     if (dtype == 0) {
         static bool set = false;
         if (!set) {

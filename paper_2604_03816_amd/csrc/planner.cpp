@@ -50,6 +50,7 @@ PlanOpts default_opts(int dtype)
         o.whole_state_max = 13;
         o.pass_budget = 224;
         o.sigma = 8;
+        o.mfma_min_k = 3;
     } else {            // complex128: 16-byte amplitudes
         o.tile_qubits = 12;
         o.low_qubits = 4;
@@ -94,7 +95,40 @@ double op_fma(const FGate& g)
     return 0.0;
 }
 
+double op_cost(const FGate& g, const PlanOpts& o)
+{
+    const double f = op_fma(g);
+    if (g.kind == OP_DENSE && o.mfma_min_k > 0 && g.k >= o.mfma_min_k) return 0.5 * f;
+    return f;
+}
+
 namespace {
+
+// Real-embedded 2D x 2D matrix of a dense complex D x D op, laid out as the A operands
+// of 16x16x4 FP32 MFMA steps: entry ((rb * KS + ks) * 64 + lane) is A[16 rb + lane % 16]
+// [4 ks + lane / 16].  Output row I <-> (element I / 2, real/imag I % 2); input column
+// kk <-> (element 4 (kk / 8) + kk % 4, real/imag (kk / 4) % 2), the order in which the
+// kernel feeds each lane's complex inputs.
+std::vector<float> mfma_operand(const std::vector<cd>& m, int k)
+{
+    const int D = 1 << k, R2 = 2 * D, RB = R2 / 16, KS = R2 / 4;
+    std::vector<float> out((size_t)R2 * R2);
+    for (int rb = 0; rb < RB; ++rb)
+        for (int ks = 0; ks < KS; ++ks)
+            for (int lane = 0; lane < 64; ++lane) {
+                const int I = 16 * rb + lane % 16, kk = 4 * ks + lane / 16;
+                const int ro = I / 2, co = I % 2;
+                const int ri = 4 * (kk / 8) + kk % 4, ci = (kk / 4) % 2;
+                const cd u = m[(size_t)ro * D + ri];
+                double v;
+                if (co == 0 && ci == 0) v = u.real();
+                else if (co == 0 && ci == 1) v = -u.imag();
+                else if (co == 1 && ci == 0) v = u.imag();
+                else v = u.real();
+                out[(size_t)(rb * KS + ks) * 64 + lane] = (float)v;
+            }
+    return out;
+}
 
 bool is_identity(const FGate& g)
 {
@@ -297,15 +331,18 @@ void run_fusion(std::vector<Node>& nodes, const PlanOpts& o)
                     if (kq > o.kmax) continue;
                     // (5), predicted: a product with a dense factor is dense (exact
                     // cancellation to a cheaper kind is rare and only costs a missed merge)
-                    if (o.cost_aware > 0 && (U.g.kind == OP_DENSE || V.g.kind == OP_DENSE) &&
-                        4.0 * (1 << kq) > op_fma(U.g) + op_fma(V.g) + o.sigma)
-                        continue;
+                    if (o.cost_aware > 0 && (U.g.kind == OP_DENSE || V.g.kind == OP_DENSE)) {
+                        FGate probe;
+                        probe.k = kq;
+                        probe.kind = OP_DENSE;
+                        if (op_cost(probe, o) > op_cost(U.g, o) + op_cost(V.g, o) + o.sigma) continue;
+                    }
                 }
                 bool ok = false;
                 FGate f = fuse_pair(U.g, V.g, o.kmax, ok);
                 if (!ok) continue;
                 // (5) arithmetic does not grow beyond what the merge saves
-                if (o.cost_aware > 0 && op_fma(f) > op_fma(U.g) + op_fma(V.g) + o.sigma) continue;
+                if (o.cost_aware > 0 && op_cost(f, o) > op_cost(U.g, o) + op_cost(V.g, o) + o.sigma) continue;
                 // merge v into u: relink the per-qubit lines
                 int nprev[kMaxK], nnext[kMaxK];
                 for (int j = 0; j < f.k; ++j) {
@@ -408,7 +445,7 @@ bool make_plan(int n, int dtype, const std::vector<InGate>& gates, const PlanOpt
             unsigned long long gm = 0;
             for (int j = 0; j < g.k; ++j) gm |= 1ull << g.q[j];
             if (gm & blocked) { blocked |= gm; continue; }
-            const double c = op_fma(g) + o.sigma;
+            const double c = op_cost(g, o) + o.sigma;
             const bool limit_ops = o.max_ops_per_pass > 0 && (int)pp.ops.size() >= o.max_ops_per_pass;
             const bool fits_budget = whole || o.pass_budget < 0 || c <= budget || pp.ops.empty();
             unsigned long long nA = (g.kind == OP_DIAG) ? A : (A | gm);
@@ -445,7 +482,7 @@ bool make_plan(int n, int dtype, const std::vector<InGate>& gates, const PlanOpt
         PassArgs a{};
         a.m = (int)pp.active.size();
         a.L = pp.low;
-        for (int i = a.L; i < a.m; ++i) a.hstride[i - a.L] = 1ll << pp.active[i];
+        for (int i = a.L; i < a.m; ++i) a.hbit[i - a.L] = (unsigned char)pp.active[i];
         a.nruns = 0;
         {
             unsigned long long A = 0;
@@ -455,8 +492,8 @@ bool make_plan(int n, int dtype, const std::vector<InGate>& gates, const PlanOpt
                 if ((A >> b) & 1) { ++b; continue; }
                 int s = b;
                 while (b < n && !((A >> b) & 1)) ++b;
-                a.run_pos[a.nruns] = s;
-                a.run_len[a.nruns] = b - s;
+                a.run_pos[a.nruns] = (unsigned char)s;
+                a.run_len[a.nruns] = (unsigned char)(b - s);
                 ++a.nruns;
             }
         }
@@ -475,9 +512,17 @@ bool make_plan(int n, int dtype, const std::vector<InGate>& gates, const PlanOpt
             }
             const int dd = 1 << g.k;
             d.off = (int)P.pool.size();
+            d.aoff = -1;
             if (g.kind == OP_DENSE) {
                 P.pool.insert(P.pool.end(), g.m.begin(), g.m.end());
                 ++P.dense_ops;
+                if (o.mfma_min_k > 0 && g.k >= o.mfma_min_k && (1 << (a.m - g.k)) >= 16) {
+                    // the operand floats ride in the complex pool, two per element
+                    const std::vector<float> A = mfma_operand(g.m, g.k);
+                    d.aoff = (int)P.pool.size();
+                    for (size_t i = 0; i < A.size(); i += 2) P.pool.push_back(cd(A[i], A[i + 1]));
+                    ++P.mfma_ops;
+                }
             } else if (g.kind == OP_DIAG) {
                 for (int r = 0; r < dd; ++r) P.pool.push_back(g.m[(size_t)r * dd + r]);
                 ++P.diag_ops;

@@ -39,6 +39,7 @@ struct PlanOpts {
     double pass_budget = 160;  // FMA per amplitude per pass (<0: unlimited)
     double sigma = 8;          // per-op on-chip cost in FMA-per-amplitude units
     int max_ops_per_pass = 0;  // 0: no limit
+    int mfma_min_k = 0;        // dense ops with k >= this run on MFMA (complex64 only); 0: never
 };
 
 struct PassPlan {
@@ -62,12 +63,17 @@ struct HostPlan {
     std::vector<cd> pool;
     std::vector<int> ipool;
     // stats
-    size_t dense_ops = 0, diag_ops = 0, perm_ops = 0;
+    size_t dense_ops = 0, diag_ops = 0, perm_ops = 0, mfma_ops = 0;
     double fma_per_amp = 0;
 };
 
-// Arithmetic cost of one op on chip, in FMA per amplitude (excluding sigma).
+// Arithmetic of one op, in FMA per amplitude (dense 4*2^k, diagonal 4, permutation 0
+// or 4 with phases).
 double op_fma(const FGate& g);
+
+// Scheduling cost of one op on chip (excluding sigma): op_fma, halved for dense ops that
+// run on FP32 MFMA (twice the non-packed VALU rate).
+double op_cost(const FGate& g, const PlanOpts& o);
 
 // Classifies a dense matrix: OP_DIAG when every off-diagonal entry is exactly zero,
 // OP_PERM when every row and column holds exactly one nonzero, else OP_DENSE.

@@ -25,23 +25,25 @@ struct DevOp {
     int off;            // offset into the complex pool: dense 4^k, diagonal 2^k, permutation 2^k phases
     int ioff;           // permutation: offset into the int pool (2^k source rows)
     int flags;          // permutation: 1 when some phase differs from 1
-    int pad;
+    int aoff;           // complex64 dense ops on MFMA: offset (complex elements) into the pool of the
+                        // real-embedded matrix in MFMA operand order, else -1
 };
 
 // Everything a pass kernel needs to place its tile in the state vector.
 // Local tile index bits 0..L-1 are physical bits 0..L-1; local bits L..m-1 are the
-// other tile qubits in ascending order with physical strides hstride[].  The tile
-// number is deposited into the remaining (free) physical bits, which form nruns
-// maximal runs (run_pos, run_len).
+// other tile qubits in ascending order, at physical bits hbit[].  The tile number is
+// deposited into the remaining (free) physical bits, which form nruns maximal runs
+// (run_pos, run_len).  Kept small (bytes) so the kernels hold it in scalar registers.
+constexpr int kMaxRuns = kMaxTileQubits + 2;
 struct PassArgs {
-    long long hstride[kMaxTileQubits];
-    int run_pos[kMaxQubits];
-    int run_len[kMaxQubits];
-    int nruns;
     int m;
     int L;
     int op_begin;
     int op_count;
+    int nruns;
+    unsigned char hbit[kMaxTileQubits];
+    unsigned char run_pos[kMaxRuns];
+    unsigned char run_len[kMaxRuns];
 };
 
 // Work list for the expectation kernel: up to kMaxTermsPerLaunch Pauli strings whose
@@ -76,6 +78,7 @@ struct MargArgs {
 };
 
 // One state's current pass inside a batched launch (continuous batching).
+constexpr int kMaxBatchItems = 256;
 struct BatchItem {
     void* state;
     const DevOp* ops;
@@ -100,7 +103,8 @@ struct ZItem {
 __host__ __device__ constexpr int kMaxTileQubitsC(int dt) { return dt == 0 ? 13 : 12; }
 
 // Launchers (kernels.hip).  dtype 0 = complex64, 1 = complex128.
-hipError_t launch_batch_pass(int dtype, const BatchItem* items, const int* count, int grid, hipStream_t s);
+hipError_t launch_batch_pass(int dtype, const BatchItem* items, const int* count, int grid, int tile_qubits,
+                             hipStream_t s);
 hipError_t launch_zsum_batch(int dtype, const ZItem* items, const int* count, double* partial, int grid,
                              hipStream_t s);
 hipError_t launch_pass(int dtype, void* st, const PassArgs& a, long long grid, const DevOp* ops,

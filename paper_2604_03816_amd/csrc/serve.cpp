@@ -42,6 +42,7 @@ bool read_gate_public(const qsv_gate& g, int n, InGate& out, std::string& err);
 namespace {
 
 constexpr int kZQ = 12;   // chunk qubits of the batched <Z> reduction (k_zsum_batch)
+constexpr int kServeTileQubits[2] = {12, 11};   // 32 KiB tiles: complex64, complex128
 
 struct Req {
     long long id = 0;
@@ -269,7 +270,8 @@ hipError_t launch_step(qsv_server s)
     const int grid = s->o.grid > 0 ? s->o.grid : 2048;
     for (int j = 0; j < P; ++j)
         for (int dt = 0; dt < 2; ++dt) {
-            hipError_t e = launch_batch_pass(dt, s->d_items[dt * P + j], s->d_count[dt * P + j], grid, s->stream);
+            hipError_t e = launch_batch_pass(dt, s->d_items[dt * P + j], s->d_count[dt * P + j], grid,
+                                             kServeTileQubits[dt], s->stream);
             if (e != hipSuccess) return e;
         }
     for (int dt = 0; dt < 2; ++dt) {
@@ -343,6 +345,7 @@ qsv_status qsv_server_create(const qsv_server_opts* opts, void* stream, qsv_serv
     qsv_server s = new qsv_server_s();
     if (opts) s->o = *opts;
     if (s->o.max_slots <= 0) s->o.max_slots = 64;
+    s->o.max_slots = std::min(s->o.max_slots, kMaxBatchItems);
     if (s->o.passes_per_step <= 0) s->o.passes_per_step = 1;
     if (s->o.planner_threads <= 0) s->o.planner_threads = 4;
     if (s->o.reserve_bytes == 0) s->o.reserve_bytes = (size_t)1 << 30;
@@ -455,7 +458,12 @@ qsv_status qsv_server_submit(qsv_server s, int n, qsv_dtype dtype, const qsv_gat
         if (popts->pass_budget != 0) r->popts.pass_budget = popts->pass_budget;
         if (!r->popts.fuse) r->popts.max_ops_per_pass = 1;
     }
-    if (r->popts.tile_qubits > kMaxTileQubitsC(dtype)) return set_error(QSV_E_ARG, "tile_qubits exceeds the LDS tile limit");
+    // served tiles are capped so every batched launch needs at most 32 KiB of LDS per
+    // workgroup (several workgroups per CU)
+    const int cap = kServeTileQubits[dtype];
+    r->popts.tile_qubits = std::min(r->popts.tile_qubits, cap);
+    r->popts.whole_state_max = std::min(r->popts.whole_state_max, cap);
+    if (r->popts.low_qubits >= r->popts.tile_qubits) r->popts.low_qubits = r->popts.tile_qubits - 1;
     r->gates.resize(n_gates);
     std::string err;
     for (size_t i = 0; i < n_gates; ++i)
