@@ -73,6 +73,7 @@ struct qsv_plan_s {
     DevOp* d_ops = nullptr;
     void* d_pool = nullptr;
     int* d_ipool = nullptr;
+    float* d_apool = nullptr;
 };
 
 namespace {
@@ -166,9 +167,11 @@ qsv_status upload_plan(qsv_plan p, int device)
         (void)hipFree(p->d_ops);
         (void)hipFree(p->d_pool);
         (void)hipFree(p->d_ipool);
+        (void)hipFree(p->d_apool);
         p->d_ops = nullptr;
         p->d_pool = nullptr;
         p->d_ipool = nullptr;
+        p->d_apool = nullptr;
         p->device = -1;
     }
     const HostPlan& hp = p->hp;
@@ -176,16 +179,20 @@ qsv_status upload_plan(qsv_plan p, int device)
     const size_t npool = std::max<size_t>(hp.pool.size(), 1);
     const size_t nipool = std::max<size_t>(hp.ipool.size(), 1);
     const size_t eb = elem_bytes(hp.dtype);
+    const size_t napool = std::max<size_t>(hp.apool.size(), 1);
     if (hipMalloc((void**)&p->d_ops, nops * sizeof(DevOp)) != hipSuccess ||
         hipMalloc(&p->d_pool, npool * eb) != hipSuccess ||
-        hipMalloc((void**)&p->d_ipool, nipool * sizeof(int)) != hipSuccess) {
+        hipMalloc((void**)&p->d_ipool, nipool * sizeof(int)) != hipSuccess ||
+        hipMalloc((void**)&p->d_apool, napool * sizeof(float)) != hipSuccess) {
         (void)hipGetLastError();
         (void)hipFree(p->d_ops);
         (void)hipFree(p->d_pool);
         (void)hipFree(p->d_ipool);
+        (void)hipFree(p->d_apool);
         p->d_ops = nullptr;
         p->d_pool = nullptr;
         p->d_ipool = nullptr;
+        p->d_apool = nullptr;
         return fail(QSV_E_OOM, "plan table allocation failed");
     }
     std::vector<unsigned char> pool(npool * eb, 0);
@@ -203,6 +210,7 @@ qsv_status upload_plan(qsv_plan p, int device)
     if (!hp.ops.empty()) QSV_HIP(hipMemcpy(p->d_ops, hp.ops.data(), hp.ops.size() * sizeof(DevOp), hipMemcpyHostToDevice));
     QSV_HIP(hipMemcpy(p->d_pool, pool.data(), pool.size(), hipMemcpyHostToDevice));
     if (!hp.ipool.empty()) QSV_HIP(hipMemcpy(p->d_ipool, hp.ipool.data(), hp.ipool.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (!hp.apool.empty()) QSV_HIP(hipMemcpy(p->d_apool, hp.apool.data(), hp.apool.size() * sizeof(float), hipMemcpyHostToDevice));
     p->device = device;
     return QSV_OK;
 }
@@ -274,8 +282,7 @@ qsv_status pauli_elements(qsv_state s, const void* sa, const void* sb, const std
 {
     const int n = s->n;
     const PlanOpts o = default_opts(s->dtype);
-    // tiles of at most 32 KiB leave room for the kernel's static reduction scratch
-    const int m = std::min(n, s->dtype == QSV_C64 ? 12 : 11);
+    const int m = std::min(n, kExpvalMaxTileQubits);
     const int L = std::min(o.low_qubits, m);
     const unsigned long long lowmask = (L >= 64) ? ~0ull : ((1ull << L) - 1);
     out.assign(terms.size(), 0.0);
@@ -382,7 +389,7 @@ qsv_status apply_gates(qsv_state s, const std::vector<InGate>& gates)
     qsv_status st = upload_plan(p, s->device);
     for (size_t i = 0; st == QSV_OK && i < p->hp.passes.size(); ++i) {
         const hipError_t e = launch_pass(s->dtype, s->buf, p->hp.pargs[i], p->hp.pgrid[i], p->d_ops, p->d_pool,
-                                         p->d_ipool, s->stream);
+                                         p->d_ipool, p->d_apool, s->stream);
         if (e != hipSuccess) st = fail(QSV_E_DEVICE, std::string("pass: ") + hipGetErrorString(e));
     }
     const hipError_t e = hipStreamSynchronize(s->stream);
@@ -390,6 +397,7 @@ qsv_status apply_gates(qsv_state s, const std::vector<InGate>& gates)
         (void)hipFree(p->d_ops);
         (void)hipFree(p->d_pool);
         (void)hipFree(p->d_ipool);
+        (void)hipFree(p->d_apool);
     }
     delete p;
     if (st == QSV_OK && e != hipSuccess) return fail(QSV_E_DEVICE, std::string("apply: ") + hipGetErrorString(e));
@@ -592,6 +600,7 @@ qsv_status qsv_plan_free(qsv_plan p)
         (void)hipFree(p->d_ops);
         (void)hipFree(p->d_pool);
         (void)hipFree(p->d_ipool);
+        (void)hipFree(p->d_apool);
     }
     delete p;
     return QSV_OK;
@@ -738,7 +747,8 @@ qsv_status qsv_plan_apply_range(qsv_state s, qsv_plan p, size_t first, size_t co
     if (st != QSV_OK) return st;
     for (size_t i = first; i < first + count; ++i) {
         const PassArgs& a = p->hp.pargs[i];
-        QSV_HIP(launch_pass(s->dtype, s->buf, a, p->hp.pgrid[i], p->d_ops, p->d_pool, p->d_ipool, s->stream));
+        QSV_HIP(launch_pass(s->dtype, s->buf, a, p->hp.pgrid[i], p->d_ops, p->d_pool, p->d_ipool, p->d_apool,
+                            s->stream));
     }
     return QSV_OK;
 }

@@ -204,12 +204,12 @@ __device__ void op_dense(C* __restrict__ lds, int T, const DevOp& op, cptr<C> __
 // lane (q, col) = (lane / 16, lane % 16) feeds group `col`, complex input rows 4 j + q
 // (real part, then imaginary part, as two K = 4 steps), and receives output rows
 // 8 rb + 2 q and 8 rb + 2 q + 1 of row block rb.  The A operands (host-arranged, see
-// the planner) stay in registers for the whole op.  All reads of a block precede its
+// the planner; staged in LDS once per kernel) stay in registers for the whole op.  All reads of a block precede its
 // writes, so the update is in place; waves own disjoint groups.
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 template <int K>
-__device__ void op_dense_mfma(float2* __restrict__ lds, int T, const DevOp& op, cptr<float> __restrict__ A)
+__device__ void op_dense_mfma(float2* __restrict__ lds, int T, const DevOp& op, const float* __restrict__ A)
 {
     constexpr int D = 1 << K, R2 = 2 * D, RB = R2 / 16, KS = R2 / 4;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -280,16 +280,16 @@ __device__ void op_diag(C* __restrict__ lds, int T, const DevOp& op, cptr<C> __r
 }
 
 template <typename C>
-__device__ void apply_ops(C* __restrict__ lds, int T, cptr<DevOp> __restrict__ ops, int op_begin,
+__device__ __forceinline__ void apply_ops(C* __restrict__ lds, int T, cptr<DevOp> __restrict__ ops, int op_begin,
                           int op_count, cptr<C> __restrict__ pool, cptr<int> __restrict__ ipool,
-                          long long base)
+                          const float* __restrict__ alds, long long base)
 {
     for (int oi = 0; oi < op_count; ++oi) {
         const DevOp op = ops[op_begin + oi];
         cptr<C> M = pool + op.off;
         if constexpr (std::is_same<C, float2>::value) {
-            if (op.kind == OP_DENSE && op.aoff >= 0 && ((T >> op.k) >> 4) > 0) {
-                cptr<float> Am = (cptr<float>)(pool + op.aoff);
+            if (op.kind == OP_DENSE && op.aoff >= 0) {
+                const float* Am = alds + op.aoff;
                 switch (op.k) {
                 case 3: op_dense_mfma<3>(lds, T, op, Am); break;
                 case 4: op_dense_mfma<4>(lds, T, op, Am); break;
@@ -323,16 +323,24 @@ __device__ void apply_ops(C* __restrict__ lds, int T, cptr<DevOp> __restrict__ o
     }
 }
 
+// The pass's MFMA operand block, global -> LDS (once per kernel, or per work item in
+// batched launches).
+__device__ __forceinline__ void stage_operands(float* __restrict__ alds, cptr<float> __restrict__ apool,
+                                               const PassArgs& a)
+{
+    for (int i = threadIdx.x; i < a.a_len; i += kThreads) alds[i] = apool[a.a_off + i];
+}
+
 // One tile of one pass: HBM -> LDS, every op of the pass, LDS -> HBM.
 template <typename C>
 __device__ __forceinline__ void run_tile(gptr<C> __restrict__ st, C* __restrict__ lds, const PassArgs& a,
                                          long long tile, cptr<DevOp> __restrict__ ops, cptr<C> __restrict__ pool,
-                                         cptr<int> __restrict__ ipool)
+                                         cptr<int> __restrict__ ipool, const float* __restrict__ alds)
 {
     const long long base = tile_base(a, tile);
     move_tile<C, true>(st, lds, a, base);
     __syncthreads();
-    apply_ops<C>(lds, 1 << a.m, ops, a.op_begin, a.op_count, pool, ipool, base);
+    apply_ops<C>(lds, 1 << a.m, ops, a.op_begin, a.op_count, pool, ipool, alds, base);
     move_tile<C, false>(st, lds, a, base);
 }
 
@@ -340,11 +348,15 @@ template <typename C>
 __global__ __launch_bounds__(kThreads) void k_pass(C* __restrict__ st, const PassArgs a,
                                                    const DevOp* __restrict__ ops,
                                                    const C* __restrict__ pool,
-                                                   const int* __restrict__ ipool)
+                                                   const int* __restrict__ ipool,
+                                                   const float* __restrict__ apool)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     C* lds = reinterpret_cast<C*>(smem);
-    run_tile<C>((gptr<C>)st, lds, a, blockIdx.x, (cptr<DevOp>)ops, (cptr<C>)pool, (cptr<int>)ipool);
+    float* alds = reinterpret_cast<float*>(smem + (sizeof(C) << a.m));
+    stage_operands(alds, (cptr<float>)apool, a);
+    __syncthreads();
+    run_tile<C>((gptr<C>)st, lds, a, blockIdx.x, (cptr<DevOp>)ops, (cptr<C>)pool, (cptr<int>)ipool, alds);
 }
 
 // Batched pass for continuous batching: one launch advances many independent states,
@@ -378,8 +390,13 @@ __global__ __launch_bounds__(kThreads) void k_batch_pass(const BatchItem* __rest
         const long long tile = w - (it.tile_end - it.ntiles);
         // pointers read from memory carry no address space: state in global memory
         // (global, not flat, loads and stores), plan tables read-only (scalar loads)
+        float* alds = reinterpret_cast<float*>(smem + (sizeof(C) << it.a.m));
+        if (it.a.a_len > 0) {
+            stage_operands(alds, (cptr<float>)it.apool, it.a);
+            __syncthreads();
+        }
         run_tile<C>((gptr<C>)it.state, lds, it.a, tile, (cptr<DevOp>)it.ops, (cptr<C>)it.pool,
-                    (cptr<int>)it.ipool);
+                    (cptr<int>)it.ipool, alds);
         __syncthreads();   // the next work item reuses the LDS tile
     }
 }
@@ -473,52 +490,154 @@ __global__ __launch_bounds__(kThreads) void k_norm(const C* __restrict__ st, lon
 
 // Pauli matrix elements over tiles: value_t = sum_k Re( i^ny conj(a[k xor x]) b[k] ) *
 // (-1)^popcount(k & zy), i.e. Re <a|P_t|b> (ny may carry an extra 3 to give Im instead).
-// Each term's X/Y support lies inside the tile, so the partner a[k xor x] is read from
-// the LDS copy of a's tile; b is a itself (expectation values) or a second state read
-// straight from HBM at the same addresses (adjoint gradients).
+// Each term's X/Y support lies inside the tile.  A thread owns local elements
+// e = 256 j + tid (j < NS) of every tile.  The sign of element e splits into a part fixed
+// by the tile and tid and a Walsh function of j, so for all terms without X/Y factors a
+// single Walsh-Hadamard transform over j of the products conj(a_e) b_e (|a_e|^2 when
+// a == b), done in registers once per tile, yields every term as one LDS lookup.  Terms
+// with X/Y factors read their partner amplitude a[e xor x] from an LDS copy of the tile.
+// FP64 per thread; the workgroup partials are combined in a fixed order.
+struct TermRow {
+    int x, z, q, pad;
+    long long g;
+};
+
+template <typename C, int NS, bool TWO>
+__device__ __forceinline__ void expval_tiles(gptr<C> __restrict__ sa, gptr<C> __restrict__ sb,
+                                             unsigned char* __restrict__ smem, const TermRow* __restrict__ rows,
+                                             const PassArgs& a, int nterms, bool anyx, long long ntiles,
+                                             double (&acc)[kMaxTermsPerLaunch])
+{
+    constexpr int LB = NS >= 32 ? 5 : NS >= 16 ? 4 : NS >= 8 ? 3 : NS >= 4 ? 2 : NS >= 2 ? 1 : 0;
+    constexpr int T = NS << kLogThreads;
+    double* wre = reinterpret_cast<double*>(smem);               // T doubles: transform of Re
+    double* wim = wre + T;                                       // T doubles: transform of Im (TWO)
+    C* tla = reinterpret_cast<C*>(smem + (TWO ? 2 : 1) * T * sizeof(double));   // tile of a (anyx)
+    C* tlb = tla + T;                                            // tile of b (anyx && TWO)
+    long long hs[LB > 0 ? LB : 1];
+#pragma unroll
+    for (int b = 0; b < LB; ++b) hs[b] = local_stride(a, kLogThreads + b);
+    const int tid = threadIdx.x;
+    const long long tl = local_off_bits(a, tid, 0, kLogThreads);
+    auto soff = [&](int j) {
+        long long so = 0;
+#pragma unroll
+        for (int b = 0; b < LB; ++b)
+            if ((j >> b) & 1) so += hs[b];
+        return so;
+    };
+    for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const long long base = tile_base(a, tile);
+        C av[NS], bv[NS];
+#pragma unroll
+        for (int j = 0; j < NS; ++j) av[j] = sa[base + tl + soff(j)];
+        if (TWO) {
+#pragma unroll
+            for (int j = 0; j < NS; ++j) bv[j] = sb[base + tl + soff(j)];
+        }
+        if (anyx) {
+#pragma unroll
+            for (int j = 0; j < NS; ++j) tla[(j << kLogThreads) + tid] = av[j];
+            if (TWO) {
+#pragma unroll
+                for (int j = 0; j < NS; ++j) tlb[(j << kLogThreads) + tid] = bv[j];
+            }
+        }
+        double re[NS], im[NS];
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            const C be = TWO ? bv[j] : av[j];
+            re[j] = (double)av[j].x * (double)be.x + (double)av[j].y * (double)be.y;
+            im[j] = TWO ? (double)av[j].x * (double)be.y - (double)av[j].y * (double)be.x : 0.0;
+        }
+        // natural-order Walsh-Hadamard transform: w[z] = sum_j (-1)^popcount(j & z) r[j]
+#pragma unroll
+        for (int h = 1; h < NS; h <<= 1) {
+#pragma unroll
+            for (int j = 0; j < NS; ++j) {
+                if (j & h) continue;
+                const double u = re[j], v = re[j | h];
+                re[j] = u + v;
+                re[j | h] = u - v;
+                if (TWO) {
+                    const double ui = im[j], vi = im[j | h];
+                    im[j] = ui + vi;
+                    im[j | h] = ui - vi;
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            wre[(j << kLogThreads) + tid] = re[j];
+            if (TWO) wim[(j << kLogThreads) + tid] = im[j];
+        }
+        __syncthreads();
+        // the term index stays a compile-time constant so that acc lives in registers;
+        // term rows come from LDS so that nothing per term is hoisted out of the tile loop
+#pragma unroll
+        for (int i = 0; i < kMaxTermsPerLaunch; ++i) {
+            if (i < nterms) {
+                const int x = __builtin_amdgcn_readfirstlane(rows[i].x);
+                const int z = __builtin_amdgcn_readfirstlane(rows[i].z);
+                const int q = __builtin_amdgcn_readfirstlane(rows[i].q);
+                const long long g = rows[i].g;
+                const int zhi = z >> kLogThreads;
+                const bool neg = (__popc(tid & z & (kThreads - 1)) + __popcll(base & g)) & 1;
+                double val;
+                if (x == 0) {
+                    const int w = (zhi << kLogThreads) + tid;
+                    const double r = wre[w], m = TWO ? wim[w] : 0.0;
+                    val = (q == 0) ? r : (q == 1) ? -m : (q == 2) ? -r : m;
+                } else {
+                    val = 0.0;
+#pragma unroll 4
+                    for (int j = 0; j < NS; ++j) {
+                        const int e = (j << kLogThreads) | tid;
+                        const C ap = tla[e ^ x];
+                        const C be = TWO ? tlb[e] : tla[e];
+                        const double pr = (double)ap.x * (double)be.x + (double)ap.y * (double)be.y;
+                        const double pi = (double)ap.x * (double)be.y - (double)ap.y * (double)be.x;
+                        const double v = (q == 0) ? pr : (q == 1) ? -pi : (q == 2) ? -pr : pi;
+                        val += (__popc(j & zhi) & 1) ? -v : v;
+                    }
+                }
+                acc[i] += neg ? -val : val;
+            }
+        }
+        __syncthreads();   // the next tile overwrites LDS
+    }
+}
+
+// LDS bytes of one k_expval workgroup for a tile of 2^m amplitudes.
+__host__ __device__ constexpr size_t expval_lds_bytes(size_t elem, int m, bool two, bool anyx)
+{
+    return ((two ? 2 : 1) * sizeof(double) + (anyx ? (two ? 2 : 1) * elem : 0)) << m;
+}
+
 template <typename C, bool TWO>
 __global__ __launch_bounds__(kThreads) void k_expval(const C* __restrict__ sa, const C* __restrict__ sb,
                                                      const PassArgs a, const TermArgs t, long long ntiles,
                                                      double* __restrict__ partial)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    C* lds = reinterpret_cast<C*>(smem);
     __shared__ NSum scratch[kThreads / 64];
-    const int T = 1 << a.m;
-    const int tid = threadIdx.x;
-    const int lowb = a.m < kLogThreads ? a.m : kLogThreads;
-    const long long tlocal = local_off_bits(a, tid, 0, lowb);
+    __shared__ TermRow rows[kMaxTermsPerLaunch];
+    bool anyx = false;
+    for (int i = 0; i < t.nterms; ++i) anyx |= t.xloc[i] != 0;
+    if (threadIdx.x < t.nterms) {
+        const int i = threadIdx.x;
+        rows[i] = TermRow{t.xloc[i], t.zloc[i], t.ny[i] & 3, 0, t.zglob[i]};
+    }
+    __syncthreads();
     double acc[kMaxTermsPerLaunch];
 #pragma unroll
     for (int i = 0; i < kMaxTermsPerLaunch; ++i) acc[i] = 0.0;
-    for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const long long base = tile_base(a, tile);
-        move_tile<C, true>((gptr<C>)const_cast<C*>(sa), lds, a, base);
-        __syncthreads();
-        int gpar[kMaxTermsPerLaunch];
-#pragma unroll
-        for (int i = 0; i < kMaxTermsPerLaunch; ++i)
-            gpar[i] = (i < t.nterms) ? (__popcll(base & t.zglob[i]) & 1) : 0;
-        for (int e0 = 0; e0 < T; e0 += kThreads) {
-            const int e = e0 + tid;
-            if (e >= T) break;
-            C be;
-            if (TWO) be = sb[base + tlocal + local_off_bits(a, e0, kLogThreads, a.m)];
-            else be = lds[e];
-#pragma unroll
-            for (int i = 0; i < kMaxTermsPerLaunch; ++i) {
-                if (i < t.nterms) {
-                    const C ap = lds[e ^ t.xloc[i]];
-                    const double re = (double)ap.x * (double)be.x + (double)ap.y * (double)be.y;
-                    const double im = (double)ap.x * (double)be.y - (double)ap.y * (double)be.x;
-                    const int q = t.ny[i] & 3;
-                    double val = (q == 0) ? re : (q == 1) ? -im : (q == 2) ? -re : im;
-                    const int par = (__popc(e & t.zloc[i]) + gpar[i]) & 1;
-                    acc[i] += par ? -val : val;
-                }
-            }
-        }
-        __syncthreads();
+    gptr<C> ga = (gptr<C>)const_cast<C*>(sa), gb = (gptr<C>)const_cast<C*>(sb);
+    switch (a.m - kLogThreads) {   // tiles of 2^8 .. 2^11 amplitudes
+    case 0: expval_tiles<C, 1, TWO>(ga, gb, smem, rows, a, t.nterms, anyx, ntiles, acc); break;
+    case 1: expval_tiles<C, 2, TWO>(ga, gb, smem, rows, a, t.nterms, anyx, ntiles, acc); break;
+    case 2: expval_tiles<C, 4, TWO>(ga, gb, smem, rows, a, t.nterms, anyx, ntiles, acc); break;
+    default: expval_tiles<C, 8, TWO>(ga, gb, smem, rows, a, t.nterms, anyx, ntiles, acc); break;
     }
 #pragma unroll
     for (int i = 0; i < kMaxTermsPerLaunch; ++i) {
@@ -529,6 +648,34 @@ __global__ __launch_bounds__(kThreads) void k_expval(const C* __restrict__ sa, c
                 partial[((long long)blockIdx.x * t.nterms + i) * 2] = r.s;
                 partial[((long long)blockIdx.x * t.nterms + i) * 2 + 1] = r.c;
             }
+        }
+    }
+}
+
+// Whole states below 256 amplitudes: one workgroup, element per thread, straight from
+// the definition (the tile is the state).
+template <typename C, bool TWO>
+__global__ __launch_bounds__(kThreads) void k_expval_small(const C* __restrict__ sa, const C* __restrict__ sb,
+                                                           int n, const TermArgs t, double* __restrict__ partial)
+{
+    __shared__ NSum scratch[kThreads / 64];
+    const int N = 1 << n;
+    const int e = threadIdx.x;
+    for (int i = 0; i < t.nterms; ++i) {
+        double val = 0.0;
+        if (e < N) {
+            const C ap = sa[e ^ t.xloc[i]];
+            const C be = TWO ? sb[e] : sa[e];
+            const double re = (double)ap.x * (double)be.x + (double)ap.y * (double)be.y;
+            const double im = (double)ap.x * (double)be.y - (double)ap.y * (double)be.x;
+            const int q = t.ny[i] & 3;
+            val = (q == 0) ? re : (q == 1) ? -im : (q == 2) ? -re : im;
+            if (__popc(e & t.zloc[i]) & 1) val = -val;
+        }
+        const NSum r = block_reduce(NSum{val, 0.0}, scratch);
+        if (threadIdx.x == 0) {
+            partial[(long long)i * 2] = r.s;
+            partial[(long long)i * 2 + 1] = r.c;
         }
     }
 }
@@ -677,27 +824,29 @@ hipError_t launch_zsum_batch(int dtype, const ZItem* items, const int* count, do
     return hipGetLastError();
 }
 
+// One workgroup per tile.
 template <typename R>
-hipError_t launch_pass_t(void* st, const PassArgs& a, long long grid, const DevOp* ops, const void* pool,
-                         const int* ipool, hipStream_t s)
+hipError_t launch_pass_t(void* st, const PassArgs& a, long long ntiles, const DevOp* ops, const void* pool,
+                         const int* ipool, const float* apool, hipStream_t s)
 {
     using C = typename CT<R>::T;
-    const size_t lds = sizeof(C) << a.m;
-    static bool attr_set = false;   // allow the full 64 KiB tile of dynamic LDS
+    static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void*)k_pass<C>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL(k_pass<C>, dim3((unsigned)grid), dim3(kThreads), lds, s, (C*)st, a, ops,
-                       (const C*)pool, ipool);
+    const size_t lds = (sizeof(C) << a.m) + sizeof(float) * (size_t)a.a_len;
+    hipLaunchKernelGGL(k_pass<C>, dim3((unsigned)ntiles), dim3(kThreads), lds, s, (C*)st, a, ops, (const C*)pool,
+                       ipool, apool);
     return hipGetLastError();
 }
 
 hipError_t launch_batch_pass(int dtype, const BatchItem* items, const int* count, int grid, int tile_qubits,
                              hipStream_t s)
 {
-    const size_t lds = (dtype == 0 ? sizeof(float2) : sizeof(double2)) << tile_qubits;
+    const size_t lds = ((dtype == 0 ? sizeof(float2) : sizeof(double2)) << tile_qubits) +
+                       (dtype == 0 ? sizeof(float) * kServeOperandFloats : 0);
     if (dtype == 0) {
         static bool set = false;
         if (!set) {
@@ -720,11 +869,11 @@ hipError_t launch_batch_pass(int dtype, const BatchItem* items, const int* count
     return hipGetLastError();
 }
 
-hipError_t launch_pass(int dtype, void* st, const PassArgs& a, long long grid, const DevOp* ops,
-                       const void* pool, const int* ipool, hipStream_t s)
+hipError_t launch_pass(int dtype, void* st, const PassArgs& a, long long ntiles, const DevOp* ops,
+                       const void* pool, const int* ipool, const float* apool, hipStream_t s)
 {
-    return dtype == 0 ? launch_pass_t<float>(st, a, grid, ops, pool, ipool, s)
-                      : launch_pass_t<double>(st, a, grid, ops, pool, ipool, s);
+    return dtype == 0 ? launch_pass_t<float>(st, a, ntiles, ops, pool, ipool, apool, s)
+                      : launch_pass_t<double>(st, a, ntiles, ops, pool, ipool, apool, s);
 }
 
 hipError_t launch_init_zero(int dtype, void* st, long long N, hipStream_t s)
@@ -765,14 +914,28 @@ hipError_t launch_expval(int dtype, const void* sa, const void* sb, const PassAr
                          long long ntiles, int grid, double* partial, hipStream_t s)
 {
     const bool two = sb != nullptr && sb != sa;
+    if (a.m < kLogThreads) {   // the whole state is one small tile (grid must be 1)
+        if (dtype == 0) {
+            auto k = two ? k_expval_small<float2, true> : k_expval_small<float2, false>;
+            hipLaunchKernelGGL(k, dim3(1), dim3(kThreads), 0, s, (const float2*)sa, (const float2*)sb, a.m, t, partial);
+        } else {
+            auto k = two ? k_expval_small<double2, true> : k_expval_small<double2, false>;
+            hipLaunchKernelGGL(k, dim3(1), dim3(kThreads), 0, s, (const double2*)sa, (const double2*)sb, a.m, t,
+                               partial);
+        }
+        return hipGetLastError();
+    }
+    if (a.m > kExpvalMaxTileQubits) return hipErrorInvalidValue;
+    bool anyx = false;
+    for (int i = 0; i < t.nterms; ++i) anyx |= t.xloc[i] != 0;
     if (dtype == 0) {
         auto k = two ? k_expval<float2, true> : k_expval<float2, false>;
-        hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), sizeof(float2) << a.m, s, (const float2*)sa,
-                           (const float2*)sb, a, t, ntiles, partial);
+        hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), expval_lds_bytes(sizeof(float2), a.m, two, anyx), s,
+                           (const float2*)sa, (const float2*)sb, a, t, ntiles, partial);
     } else {
         auto k = two ? k_expval<double2, true> : k_expval<double2, false>;
-        hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), sizeof(double2) << a.m, s, (const double2*)sa,
-                           (const double2*)sb, a, t, ntiles, partial);
+        hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), expval_lds_bytes(sizeof(double2), a.m, two, anyx), s,
+                           (const double2*)sa, (const double2*)sb, a, t, ntiles, partial);
     }
     return hipGetLastError();
 }

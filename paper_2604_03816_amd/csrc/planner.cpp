@@ -499,6 +499,8 @@ bool make_plan(int n, int dtype, const std::vector<InGate>& gates, const PlanOpt
         }
         a.op_begin = (int)P.ops.size();
         a.op_count = (int)pp.ops.size();
+        a.a_off = (int)P.apool.size();
+        a.a_len = 0;
         for (const int fi : pp.ops) {
             const FGate& g = P.fused[fi];
             DevOp d{};
@@ -516,11 +518,13 @@ bool make_plan(int n, int dtype, const std::vector<InGate>& gates, const PlanOpt
             if (g.kind == OP_DENSE) {
                 P.pool.insert(P.pool.end(), g.m.begin(), g.m.end());
                 ++P.dense_ops;
-                if (o.mfma_min_k > 0 && g.k >= o.mfma_min_k && (1 << (a.m - g.k)) >= 16) {
-                    // the operand floats ride in the complex pool, two per element
+                const int af = 4 << (2 * g.k);   // (2 * 2^k)^2 floats
+                if (o.mfma_min_k > 0 && g.k >= o.mfma_min_k && (1 << (a.m - g.k)) >= 16 &&
+                    a.a_len + af <= o.mfma_lds_floats) {
                     const std::vector<float> A = mfma_operand(g.m, g.k);
-                    d.aoff = (int)P.pool.size();
-                    for (size_t i = 0; i < A.size(); i += 2) P.pool.push_back(cd(A[i], A[i + 1]));
+                    d.aoff = a.a_len;
+                    P.apool.insert(P.apool.end(), A.begin(), A.end());
+                    a.a_len += af;
                     ++P.mfma_ops;
                 }
             } else if (g.kind == OP_DIAG) {

@@ -40,6 +40,7 @@ struct PlanOpts {
     double sigma = 8;          // per-op on-chip cost in FMA-per-amplitude units
     int max_ops_per_pass = 0;  // 0: no limit
     int mfma_min_k = 0;        // dense ops with k >= this run on MFMA (complex64 only); 0: never
+    int mfma_lds_floats = 2048;  // per-pass cap of MFMA operand floats staged in LDS
 };
 
 struct PassPlan {
@@ -62,6 +63,7 @@ struct HostPlan {
     std::vector<long long> pgrid;  // tiles per pass
     std::vector<cd> pool;
     std::vector<int> ipool;
+    std::vector<float> apool;      // MFMA operand blocks, one contiguous block per pass
     // stats
     size_t dense_ops = 0, diag_ops = 0, perm_ops = 0, mfma_ops = 0;
     double fma_per_amp = 0;

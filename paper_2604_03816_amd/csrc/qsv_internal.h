@@ -25,8 +25,8 @@ struct DevOp {
     int off;            // offset into the complex pool: dense 4^k, diagonal 2^k, permutation 2^k phases
     int ioff;           // permutation: offset into the int pool (2^k source rows)
     int flags;          // permutation: 1 when some phase differs from 1
-    int aoff;           // complex64 dense ops on MFMA: offset (complex elements) into the pool of the
-                        // real-embedded matrix in MFMA operand order, else -1
+    int aoff;           // complex64 dense op on MFMA: float offset of its real-embedded matrix (MFMA
+                        // operand order) inside the pass's operand block in LDS, else -1
 };
 
 // Everything a pass kernel needs to place its tile in the state vector.
@@ -41,6 +41,8 @@ struct PassArgs {
     int op_begin;
     int op_count;
     int nruns;
+    int a_off;          // the pass's MFMA operand block: float offset in the plan's operand array
+    int a_len;          // and its length in floats (staged into LDS behind the tile)
     unsigned char hbit[kMaxTileQubits];
     unsigned char run_pos[kMaxRuns];
     unsigned char run_len[kMaxRuns];
@@ -49,6 +51,10 @@ struct PassArgs {
 // Work list for the expectation kernel: up to kMaxTermsPerLaunch Pauli strings whose
 // X/Y supports all lie inside the tile.
 constexpr int kMaxTermsPerLaunch = 32;
+// Tile qubits of the Pauli matrix-element kernel (2^11 amplitudes: the per-tile Walsh
+// transforms and the tile copy of two complex128 states fit 64 KiB of LDS).
+constexpr int kExpvalMaxTileQubits = 11;
+
 struct TermArgs {
     int nterms;
     int xloc[kMaxTermsPerLaunch];          // X/Y support as tile-local bit mask
@@ -84,6 +90,7 @@ struct BatchItem {
     const DevOp* ops;
     const void* pool;
     const int* ipool;
+    const float* apool;
     long long ntiles;     // tiles of this pass
     long long tile_end;   // prefix sum of ntiles over the items up to and including this one
     PassArgs a;
@@ -99,6 +106,10 @@ struct ZItem {
     long long partial_off;  // first double of this state's partials (13 per chunk)
 };
 
+// MFMA operand floats a served complex64 pass may stage in LDS (the batched launch
+// reserves this much behind the tile).
+constexpr int kServeOperandFloats = 2048;
+
 // Largest tile (log2 amplitudes) a dtype's pass kernel holds in LDS (64 KiB).
 __host__ __device__ constexpr int kMaxTileQubitsC(int dt) { return dt == 0 ? 13 : 12; }
 
@@ -107,8 +118,8 @@ hipError_t launch_batch_pass(int dtype, const BatchItem* items, const int* count
                              hipStream_t s);
 hipError_t launch_zsum_batch(int dtype, const ZItem* items, const int* count, double* partial, int grid,
                              hipStream_t s);
-hipError_t launch_pass(int dtype, void* st, const PassArgs& a, long long grid, const DevOp* ops,
-                       const void* pool, const int* ipool, hipStream_t s);
+hipError_t launch_pass(int dtype, void* st, const PassArgs& a, long long ntiles, const DevOp* ops,
+                       const void* pool, const int* ipool, const float* apool, hipStream_t s);
 hipError_t launch_init_zero(int dtype, void* st, long long N, hipStream_t s);
 hipError_t launch_zero(int dtype, void* st, long long N, hipStream_t s);
 int norm_grid(long long N);

@@ -60,6 +60,7 @@ struct Req {
     DevOp* d_ops = nullptr;
     void* d_pool = nullptr;
     int* d_ipool = nullptr;
+    float* d_apool = nullptr;
     size_t next_pass = 0;
     double t_submit = 0, t_admit = 0, t_finish = 0;
     long long z_off = 0;   // partial offset while finishing
@@ -136,7 +137,7 @@ void worker_loop(qsv_server s)
             const HostPlan& hp = r->plan;
             r->state_bytes = elem(r->dtype) << r->n;
             r->table_bytes = hp.ops.size() * sizeof(DevOp) + hp.pool.size() * elem(r->dtype) +
-                             hp.ipool.size() * sizeof(int) + 3 * 256;
+                             hp.ipool.size() * sizeof(int) + hp.apool.size() * sizeof(float) + 4 * 256;
             const long long chunks = 1ll << std::max(0, r->n - kZQ);
             r->work_bytes = (size_t)chunks * (kZQ + 1) * sizeof(double);
             r->footprint = r->state_bytes + r->table_bytes + r->work_bytes;   // Eq. 14
@@ -201,8 +202,10 @@ qsv_status admit(qsv_server s, const std::shared_ptr<Req>& r)
     r->state = pool_get(s, r->state_bytes);
     if (!r->state) return set_error(QSV_E_OOM, "state allocation failed");
     const size_t nops = hp.ops.size() * sizeof(DevOp), npool = hp.pool.size() * eb, nip = hp.ipool.size() * sizeof(int);
+    const size_t nap = hp.apool.size() * sizeof(float);
     const size_t o_pool = (nops + 255) & ~size_t(255), o_ip = o_pool + ((npool + 255) & ~size_t(255));
-    r->table_cap = o_ip + ((nip + 255) & ~size_t(255)) + 256;
+    const size_t o_ap = o_ip + ((nip + 255) & ~size_t(255));
+    r->table_cap = o_ap + ((nap + 255) & ~size_t(255)) + 256;
     r->tables = pool_get(s, r->table_cap);
     if (!r->tables) {
         pool_put(s, r->state, r->state_bytes);
@@ -212,6 +215,7 @@ qsv_status admit(qsv_server s, const std::shared_ptr<Req>& r)
     r->d_ops = (DevOp*)r->tables;
     r->d_pool = (char*)r->tables + o_pool;
     r->d_ipool = (int*)((char*)r->tables + o_ip);
+    r->d_apool = (float*)((char*)r->tables + o_ap);
     if (!s->o.dry_run) {
         std::vector<unsigned char> buf(r->table_cap, 0);
         if (nops) std::memcpy(buf.data(), hp.ops.data(), nops);
@@ -227,6 +231,7 @@ qsv_status admit(qsv_server s, const std::shared_ptr<Req>& r)
             }
         }
         if (nip) std::memcpy(buf.data() + o_ip, hp.ipool.data(), nip);
+        if (nap) std::memcpy(buf.data() + o_ap, hp.apool.data(), nap);
         hipError_t e = hipMemcpyAsync(r->tables, buf.data(), r->table_cap, hipMemcpyHostToDevice, s->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(s->stream);   // buf is pageable and goes out of scope
         if (e == hipSuccess) e = launch_init_zero(r->dtype, r->state, 1ll << r->n, s->stream);
@@ -463,6 +468,7 @@ qsv_status qsv_server_submit(qsv_server s, int n, qsv_dtype dtype, const qsv_gat
     const int cap = kServeTileQubits[dtype];
     r->popts.tile_qubits = std::min(r->popts.tile_qubits, cap);
     r->popts.whole_state_max = std::min(r->popts.whole_state_max, cap);
+    r->popts.mfma_lds_floats = std::min(r->popts.mfma_lds_floats, kServeOperandFloats);
     if (r->popts.low_qubits >= r->popts.tile_qubits) r->popts.low_qubits = r->popts.tile_qubits - 1;
     r->gates.resize(n_gates);
     std::string err;
@@ -558,6 +564,7 @@ qsv_status qsv_server_step(qsv_server s, int* n_running, int* n_pending)
             it.ops = r->d_ops;
             it.pool = r->d_pool;
             it.ipool = r->d_ipool;
+            it.apool = r->d_apool;
             it.a = hp.pargs[pi];
             it.ntiles = hp.pgrid[pi];
             it.tile_end = (cnt ? s->h_items[slot][cnt - 1].tile_end : 0) + it.ntiles;
