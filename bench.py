@@ -14,13 +14,22 @@ GB/s": every fused gate must read and write each amplitude once; several fused g
 share one HBM round trip, so the figure can exceed the HBM peak).
 
 roofline: the pass kernel.  Algorithmic bytes per launch = 2 x 2^n x bytes-per-amplitude
-(one read and one write of the state); the average launch duration comes from HIP
-events around single-pass launches on the state's stream.
+(one read and one write of the state); algorithmic flops per launch = 2 x (the plan's
+complex-arithmetic FMA per amplitude / passes) x 2^n.  The average launch duration comes
+from HIP events recorded around every pass launch inside the timed steps, on the
+state's stream.  The bound reported is the larger fraction: HBM (8 TB/s) or ALU, whose
+peak combines the VALU rate for the VALU share of the FMA (78.6 TFLOP/s: FP64 vector,
+and FP32 without packed math) with the FP32 matrix-core rate (157.3 TFLOP/s) for the
+matrix-core share.  traffic = HBM bytes per launch measured with rocprofv3 counters
+(FETCH_SIZE + WRITE_SIZE, scaled by the same counters' reading for a device copy of
+known size), taken from the summary under profiles/ when that summary was made from
+the current kernel source, else null.
 
 cpu_baseline: the FP64 CPU oracle (gate by gate, all host threads) on the first gates of
 the same 30-qubit circuit, reported in the same unit with its own (unfused) gate count.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-c128]
+       [--no-serve] [--no-precision] [--no-adjoint] [--copy-probe]
 """
 import argparse
 import json
@@ -36,6 +45,9 @@ HBM_PEAK_GBS = 8000.0
 # VALU peak without packed FP32 (disabled in this build): 256 CUs x 64 FMA lanes per clock
 # x 2 flops x 2.4 GHz = 78.6 TFLOP/s, which is also MI355X's FP64 vector peak.
 VALU_PEAK_TFLOPS = 78.6
+MFMA_FP32_PEAK_TFLOPS = 157.3
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pass_brickwork30_hbm_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2604_03816_amd", "csrc", f) for f in ("kernels.hip", "planner.cpp")]
 
 
 def parse():
@@ -57,43 +69,84 @@ def parse():
     ap.add_argument("--adjoint-batch", type=int, default=64)
     ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--plain-requests", type=int, default=256)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="copy 4 GiB device to device once before the timed steps (counter calibration)")
     return ap.parse_args()
 
 
 def time_steps(torch, qsv, state, plan, terms, steps, warmup):
-    def step():
+    """Wall time per step, and the device time of every pass launch inside the timed
+    steps (HIP events on the state's stream, around each single-pass launch)."""
+    npass = plan.stats()["passes"]
+    stream = state.stream
+
+    def step(evs):
         state.reset()
-        state.apply_plan(plan)
+        for i in range(npass):
+            if evs is not None:
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                state.apply_plan(plan, i, 1)
+                b.record(stream)
+                evs.append((a, b))
+            else:
+                state.apply_plan(plan, i, 1)
         state.norm()
         state.expval(terms)
 
     for _ in range(warmup):
-        step()
+        step(None)
     torch.cuda.synchronize()
+    evs = []
     t0 = time.perf_counter()
     for _ in range(steps):
-        step()
+        step(evs)
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / steps
+    sec = (time.perf_counter() - t0) / steps
+    times = [a.elapsed_time(b) for a, b in evs]
+    return sec, sum(times) / len(times)
 
 
-def pass_durations(torch, state, plan, reps=2):
-    """Average device time of one pass launch, from HIP events on the state's stream."""
-    npass = plan.stats()["passes"]
-    stream = state.stream
-    times = []
-    for _ in range(reps):
-        evs = []
-        for i in range(npass):
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            state.apply_plan(plan, i, 1)
-            b.record(stream)
-            evs.append((a, b))
-        torch.cuda.synchronize()
-        times += [a.elapsed_time(b) for a, b in evs]
-    return sum(times) / len(times)
+def source_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(dtype):
+    """HBM bytes per pass launch from the committed counter summary, or None when the
+    summary is missing or was taken from other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            kv = {}
+            for line in fh:
+                line = line.strip()
+                if line.startswith("- ") and ":" in line:
+                    k, v = line[2:].split(":", 1)
+                    kv[k.strip()] = v.strip()
+    except OSError:
+        return None
+    if kv.get("kernel_sources_sha256") != source_digest():
+        return None
+    v = kv.get("%s_hbm_bytes_per_launch" % dtype)
+    return float(v) if v not in (None, "", "null") else None
+
+
+def copy_probe(torch):
+    """One 4 GiB device-to-device copy: the reference reading for HBM byte counters."""
+    nbytes = 4 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes_read": nbytes, "bytes_written": nbytes}
 
 
 def run_dtype(torch, qsv, C, args, dtype, ops, terms):
@@ -103,24 +156,28 @@ def run_dtype(torch, qsv, C, args, dtype, ops, terms):
     plan_ms = (time.perf_counter() - t0) * 1e3
     st = plan.stats()
     state = qsv.State(n, dtype)
-    sec = time_steps(torch, qsv, state, plan, terms, args.steps, args.warmup)
-    avg_pass_ms = pass_durations(torch, state, plan)
+    sec, avg_pass_ms = time_steps(torch, qsv, state, plan, terms, args.steps, args.warmup)
     elem = 8 if dtype == "c64" else 16
     pass_bytes = 2.0 * (2 ** n) * elem
     value = st["fused_out"] * pass_bytes / sec / 1e9
     achieved = pass_bytes / (avg_pass_ms * 1e-3) / 1e9
     # arithmetic of the average pass: the plan's FMA per amplitude (dense 4*2^k, diagonal
     # or phased permutation 4), 2 flops each, over every amplitude
-    pass_flops = 2.0 * st["fma_per_amp"] / st["passes"] * (2 ** n)
+    fma_v = (st["fma_per_amp"] - st["mfma_fma_per_amp"]) / st["passes"]
+    fma_m = st["mfma_fma_per_amp"] / st["passes"]
+    pass_flops = 2.0 * (fma_v + fma_m) * (2 ** n)
+    floor_s = 2.0 * (2 ** n) * (fma_v / (VALU_PEAK_TFLOPS * 1e12) + fma_m / (MFMA_FP32_PEAK_TFLOPS * 1e12))
+    alu_peak = pass_flops / floor_s / 1e12
     alu_tflops = pass_flops / (avg_pass_ms * 1e-3) / 1e12
     hbm_frac = achieved / HBM_PEAK_GBS
-    alu_frac = alu_tflops / VALU_PEAK_TFLOPS
+    alu_frac = alu_tflops / alu_peak
+    traffic = measured_traffic(dtype)
     if alu_frac > hbm_frac:
-        roof = {"bound": "alu", "achieved": alu_tflops, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": alu_frac, "traffic": None}
+        roof = {"bound": "alu", "achieved": alu_tflops, "peak": alu_peak, "unit": "TFLOP/s",
+                "frac": alu_frac, "traffic": traffic}
     else:
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": hbm_frac, "traffic": None}
+                "frac": hbm_frac, "traffic": traffic}
     # sanity of the result: the circuit preserves the norm
     norm = state.norm()
     out = {
@@ -134,7 +191,10 @@ def run_dtype(torch, qsv, C, args, dtype, ops, terms):
         "norm_minus_1": norm - 1.0,
         "roofline": roof,
         "hbm": {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm_frac},
-        "alu": {"achieved": alu_tflops, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": alu_frac},
+        "alu": {"achieved": alu_tflops, "peak": alu_peak, "unit": "TFLOP/s", "frac": alu_frac,
+                "fma_per_amp_valu": fma_v, "fma_per_amp_mfma": fma_m},
+        "traffic_bytes_per_launch": traffic,
+        "algorithmic_bytes_per_launch": pass_bytes,
     }
     state.free()
     plan.free()
@@ -281,6 +341,7 @@ def main():
         import __graft_entry__
         __graft_entry__.build()
     n = args.qubits
+    probe = copy_probe(torch) if args.copy_probe else None
     ops = C.brickwork(n, args.depth, args.seed)
     terms = C.zz_chain_terms(n)
     main_rec = run_dtype(torch, qsv, C, args, "c64", ops, terms)
@@ -305,6 +366,8 @@ def main():
         "hbm_frac": main_rec["hbm"]["frac"],
         "detail": {k: main_rec[k] for k in ("plan_ms", "avg_pass_ms", "norm_minus_1", "hbm", "alu")},
     }
+    if probe is not None:
+        rec["copy_probe"] = probe
     if not args.no_c128:
         r = run_dtype(torch, qsv, C, args, "c128", ops, terms)
         rec["c128"] = {"value": r["value"], "unit": "GB/s", "dtype": "f64", "ms_per_step": r["ms_per_step"],

@@ -126,6 +126,7 @@ typedef struct {
     size_t mfma_ops;       /* dense complex64 ops run on FP32 matrix cores */
     double fma_per_amp;    /* complex-arithmetic cost summed over all passes */
     double hbm_bytes;      /* algorithmic HBM bytes per application = passes * 2 * 2^n * elem */
+    double mfma_fma_per_amp;  /* the part of fma_per_amp done by the matrix-core ops */
 } qsv_plan_stats;
 
 /* Fuses the gate list with Algorithm 2 (Section 5.2; Eq. 9 products in FP64; a fused

@@ -618,6 +618,7 @@ qsv_status qsv_plan_get_stats(qsv_plan p, qsv_plan_stats* st)
     st->perm_ops = hp.perm_ops;
     st->mfma_ops = hp.mfma_ops;
     st->fma_per_amp = hp.fma_per_amp;
+    st->mfma_fma_per_amp = hp.mfma_fma_per_amp;
     st->hbm_bytes = (double)hp.passes.size() * 2.0 * (double)(elem_bytes(hp.dtype) << hp.n);
     return QSV_OK;
 }

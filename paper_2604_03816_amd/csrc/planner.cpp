@@ -526,6 +526,7 @@ bool make_plan(int n, int dtype, const std::vector<InGate>& gates, const PlanOpt
                     P.apool.insert(P.apool.end(), A.begin(), A.end());
                     a.a_len += af;
                     ++P.mfma_ops;
+                    P.mfma_fma_per_amp += op_fma(g);
                 }
             } else if (g.kind == OP_DIAG) {
                 for (int r = 0; r < dd; ++r) P.pool.push_back(g.m[(size_t)r * dd + r]);

@@ -66,7 +66,7 @@ struct HostPlan {
     std::vector<float> apool;      // MFMA operand blocks, one contiguous block per pass
     // stats
     size_t dense_ops = 0, diag_ops = 0, perm_ops = 0, mfma_ops = 0;
-    double fma_per_amp = 0;
+    double fma_per_amp = 0, mfma_fma_per_amp = 0;
 };
 
 // Arithmetic of one op, in FMA per amplitude (dense 4*2^k, diagonal 4, permutation 0

@@ -43,7 +43,8 @@ class PlanOpts(ctypes.Structure):
 class PlanStats(ctypes.Structure):
     _fields_ = [("gates_in", ctypes.c_size_t), ("fused_out", ctypes.c_size_t), ("passes", ctypes.c_size_t),
                 ("dense_ops", ctypes.c_size_t), ("diag_ops", ctypes.c_size_t), ("perm_ops", ctypes.c_size_t),
-                ("mfma_ops", ctypes.c_size_t), ("fma_per_amp", ctypes.c_double), ("hbm_bytes", ctypes.c_double)]
+                ("mfma_ops", ctypes.c_size_t), ("fma_per_amp", ctypes.c_double), ("hbm_bytes", ctypes.c_double),
+                ("mfma_fma_per_amp", ctypes.c_double)]
 
     def as_dict(self):
         return {f[0]: getattr(self, f[0]) for f in self._fields_}
