@@ -29,7 +29,7 @@ cpu_baseline: the FP64 CPU oracle (gate by gate, all host threads) on the first 
 the same 30-qubit circuit, reported in the same unit with its own (unfused) gate count.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-c128]
-       [--no-serve] [--no-precision] [--no-adjoint] [--copy-probe]
+       [--no-serve] [--no-precision] [--no-adjoint] [--no-sampling] [--copy-probe]
 """
 import argparse
 import json
@@ -64,6 +64,7 @@ def parse():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-sampling", action="store_true")
     ap.add_argument("--precision-qubits", type=int, nargs="*", default=[30, 32])
     ap.add_argument("--adjoint-qubits", type=int, default=24)
     ap.add_argument("--adjoint-batch", type=int, default=64)
@@ -328,6 +329,33 @@ def adjoint_bench(args):
     return out
 
 
+def sampling_bench(args, ops):
+    """Measurement sampling (inverse transform of the Born distribution) on the headline
+    state: the 30-qubit brickwork in complex64, 2^20 shots over all qubits and over 8
+    qubits; uniforms from seed 8.  Wall time of the synchronous call (host sort of the
+    shots, one chunk-total pass over the state, one pass over the chunks that hold shots)."""
+    import numpy as np
+    import torch
+    from paper_2604_03816_amd import qsv
+    n = args.qubits
+    plan = qsv.Plan(n, "c64", ops)
+    s = qsv.State(n, "c64")
+    s.apply_plan(plan)
+    s.sync()
+    u = np.random.default_rng(8).random(1 << 20)
+    out = {"n": n, "shots": int(u.size)}
+    for name, qubits in (("all_qubits", None), ("8_qubits", [0, 5, 9, 13, 17, 21, 25, 29][: min(8, n)])):
+        s.sample(u[:1024], qubits)
+        t0 = time.perf_counter()
+        got = s.sample(u, qubits)
+        wall = time.perf_counter() - t0
+        out[name] = {"wall_s": wall, "shots_per_s": u.size / wall, "distinct_outcomes": int(np.unique(got).size)}
+    s.free()
+    plan.free()
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -380,6 +408,8 @@ def main():
         rec["precision"] = precision_study(args)
     if not args.no_adjoint:
         rec["adjoint"] = adjoint_bench(args)
+    if not args.no_sampling:
+        rec["sampling"] = sampling_bench(args, ops)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(C, args, ops)
     print(json.dumps(rec))

@@ -59,9 +59,10 @@ const char* qsv_version(void);
  * n_qubits in [1, 34].  buf == NULL: the library allocates 2^n * elem bytes of device
  * memory on the current HIP device and owns it.  buf != NULL: the library adopts the
  * caller's device buffer (e.g. a torch tensor's data_ptr) of buf_bytes >= 2^n * elem
- * bytes and never frees it.  stream: hipStream_t used for all device work on this
- * state (NULL = default stream).  Errors: QSV_E_ARG (n out of range, buffer too small,
- * out == NULL), QSV_E_OOM (allocation failed), QSV_E_DEVICE. */
+ * bytes, 16-byte aligned, and never frees it.  stream: hipStream_t used for all device
+ * work on this state (NULL = default stream).  Errors: QSV_E_ARG (n out of range,
+ * buffer too small or misaligned, out == NULL), QSV_E_OOM (allocation failed),
+ * QSV_E_DEVICE. */
 qsv_status qsv_alloc(int n_qubits, qsv_dtype dtype, void* buf, size_t buf_bytes,
                      void* stream, qsv_state* out);
 
@@ -107,7 +108,8 @@ qsv_status qsv_gate_matrix(const char* name, const double* params, int* k, doubl
 /* Planner options.  Zero-initialise and set what you need; 0 selects the default. */
 typedef struct {
     int fuse;            /* 0: no fusion, one gate per HBM pass (the plain path);
-                            1: DAG fusion (Algorithm 2) + multi-gate passes (default) */
+                            1: DAG fusion (Algorithm 2) + multi-gate passes (default);
+                            2: no fusion, but consecutive gates share HBM passes */
     int kmax;            /* fusion width q_max^fuse in [1, 5]; default 5 */
     int cost_aware;      /* 1 (default): only fuse when the fused op costs no more
                             arithmetic than its parts (Eq. 13 trade-off); -1: pure
@@ -116,6 +118,8 @@ typedef struct {
     int low_qubits;      /* contiguous low qubits kept in every tile, 0 = default */
     double pass_budget;  /* per-pass arithmetic budget (FMA per amplitude), 0 = default,
                             < 0 = unlimited */
+    int matrix_cores;    /* complex64 dense ops on >= this many targets run on FP32 matrix
+                            cores (MFMA): 0 = default (3), -1 = never; in [3, 5] otherwise */
 } qsv_plan_opts;
 
 typedef struct {
@@ -202,6 +206,22 @@ qsv_status qsv_expval_pauli(qsv_state s, const qsv_pauli_term* terms, size_t n_t
  * FP64.  out is device memory when out_on_device != 0, else host memory (then the
  * call synchronises).  Errors: QSV_E_ARG. */
 qsv_status qsv_probs(qsv_state s, const int* qubits, int m, void* out, int out_on_device);
+
+/* Measurement sampling in the computational basis (the backend's third operation,
+ * Section 4; Born probabilities of Eq. 1).  Measures `qubits` (m distinct qubits, bit j
+ * of an outcome <-> qubits[j]; NULL = all n in order) once per uniform: shot i's outcome
+ * is the smallest k with uniforms[i] * P < p_0 + ... + p_k, where p is the distribution
+ * over the measured qubits accumulated in FP64 and P its total (an unnormalised state is
+ * sampled from its normalised distribution); an outcome of probability zero is never
+ * returned.  The caller supplies the random numbers (host array of `shots` values in
+ * [0, 1)), so results are reproducible.  out: host array of `shots` outcomes.  The
+ * partial sums are taken in a fixed order, so the call is deterministic; where u * P
+ * falls within rounding of a boundary between two outcomes either may be returned.
+ * Synchronous.  Errors: QSV_E_ARG (bad qubits, a uniform outside [0, 1), null
+ * pointers), QSV_E_UNSUPPORTED (a marginal or reordered distribution over more than 26
+ * qubits), QSV_E_OOM. */
+qsv_status qsv_sample(qsv_state s, const int* qubits, int m, const double* uniforms, long long shots,
+                      long long* out);
 
 /* ------------------------------------------------------------------ gradients */
 

@@ -15,6 +15,9 @@ definitions that sit on top:
                               (the parameter-shift rule the paper's PennyLane path uses,
                               Section 7.4), evaluated with ``simulate`` + ``expval``
 * ``fd_grad``             -- central finite differences
+* ``sample``              -- computational-basis measurement sampling by inverse
+                              transform of the Born probabilities (Eq. 1), the
+                              backend's third operation (Section 4)
 """
 from __future__ import annotations
 
@@ -128,6 +131,21 @@ def probs(psi: np.ndarray, qubits: Sequence[int] = None) -> np.ndarray:
     if lib().or_probs(_ptr(psi), n, _ptr(q), len(q), _ptr(out)) != 0:
         raise ValueError("bad qubits")
     return out
+
+
+def sample(psi: np.ndarray, qubits: Sequence[int], uniforms: np.ndarray) -> np.ndarray:
+    """Outcomes of measuring ``qubits`` (bit j of an outcome <-> qubits[j]), one per
+    uniform u in [0, 1): the smallest k with u * P < p_0 + ... + p_k, where p is the
+    marginal Born distribution over ``qubits`` and P its total (so an unnormalised
+    state is sampled from its normalised distribution).  The running sum is plain
+    sequential FP64; an outcome of probability zero is never returned."""
+    p = probs(psi, qubits)
+    c = np.cumsum(p)
+    u = np.asarray(uniforms, dtype=np.float64)
+    if np.any(u < 0) or np.any(u >= 1):
+        raise ValueError("uniforms must lie in [0, 1)")
+    k = np.searchsorted(c, u * c[-1], side="right")
+    return np.minimum(k, np.flatnonzero(p)[-1]).astype(np.int64)
 
 
 def pauli_expval(psi: np.ndarray, string: Sequence[Tuple[int, str]]) -> complex:

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdint>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -261,7 +262,7 @@ PassArgs tile_args(int n, int m, int L, unsigned long long need, std::vector<int
     PassArgs a{};
     a.m = (int)active.size();
     a.L = std::min(L, a.m);
-    for (int i = a.L; i < a.m; ++i) a.hbit[i - a.L] = (unsigned char)active[i];
+    for (int i = 0; i < a.m; ++i) a.phys[i] = (unsigned char)active[i];
     int b = 0;
     while (b < n) {
         if ((A >> b) & 1) { ++b; continue; }
@@ -420,6 +421,7 @@ qsv_status qsv_alloc(int n, qsv_dtype dtype, void* buf, size_t buf_bytes, void* 
     if (dtype != QSV_C64 && dtype != QSV_C128) return fail(QSV_E_ARG, "bad dtype");
     const size_t bytes = elem_bytes(dtype) << n;
     if (buf && buf_bytes < bytes) return fail(QSV_E_ARG, "adopted buffer is smaller than 2^n amplitudes");
+    if (buf && ((uintptr_t)buf & 15)) return fail(QSV_E_ARG, "adopted buffer must be 16-byte aligned");
     int dev = 0;
     QSV_HIP(hipGetDevice(&dev));
     qsv_state s = new qsv_state_s();
@@ -567,16 +569,9 @@ qsv_status qsv_plan_create(int n, qsv_dtype dtype, const qsv_gate* gates, size_t
     if (n < 1 || n > kMaxQubits) return fail(QSV_E_ARG, "n_qubits must be in [1, 34]");
     if (dtype != QSV_C64 && dtype != QSV_C128) return fail(QSV_E_ARG, "bad dtype");
     if (n_gates && !gates) return fail(QSV_E_ARG, "gates is null");
-    PlanOpts o = default_opts(dtype);
-    if (opts) {
-        o.fuse = opts->fuse;
-        if (opts->kmax) o.kmax = opts->kmax;
-        if (opts->cost_aware) o.cost_aware = opts->cost_aware;
-        if (opts->tile_qubits) o.tile_qubits = opts->tile_qubits;
-        if (opts->low_qubits) o.low_qubits = opts->low_qubits;
-        if (opts->pass_budget != 0) o.pass_budget = opts->pass_budget;
-    }
-    if (!o.fuse) o.max_ops_per_pass = 1;
+    PlanOpts o;
+    std::string oerr;
+    if (!plan_opts_from(dtype, opts, o, oerr)) return fail(QSV_E_ARG, oerr);
     const int max_tile = dtype == QSV_C64 ? 13 : 12;   // 64 KiB of LDS
     if (o.tile_qubits > max_tile) return fail(QSV_E_ARG, "tile_qubits exceeds the LDS tile limit");
     std::vector<InGate> in(n_gates);
@@ -675,7 +670,7 @@ qsv_status qsv_plan_emulate(qsv_plan p, double* state)
         for (int e = 0; e < T; ++e) {
             long long o = 0;
             for (int i = 0; i < a.m; ++i)
-                if ((e >> i) & 1) o += (i < a.L) ? (1ll << i) : (1ll << a.hbit[i - a.L]);
+                if ((e >> i) & 1) o += 1ll << a.phys[i];
             off[e] = o;
         }
         for (long long t = 0; t < hp.pgrid[pi]; ++t) {
@@ -893,6 +888,112 @@ qsv_status qsv_probs(qsv_state s, const int* qubits, int m, void* out, int out_o
 // Consecutive rotations on distinct qubits commute, so every rotation of such a layer
 // is evaluated at the layer's end in one read pass over (lambda, phi); between
 // evaluation points phi and lambda are uncomputed with one fused plan of inverse gates.
+namespace {
+
+// Device scratch owned by one call; freed on every exit path.
+struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf() { if (p) (void)hipFree(p); }
+    bool alloc(size_t bytes)
+    {
+        if (hipMalloc(&p, bytes ? bytes : 16) != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            return false;
+        }
+        return true;
+    }
+};
+
+}  // namespace
+
+qsv_status qsv_sample(qsv_state s, const int* qubits, int m, const double* uniforms, long long shots,
+                      long long* out)
+{
+    qsv_status st = check_state(s);
+    if (st != QSV_OK) return st;
+    const int n = s->n;
+    if (shots < 0) return fail(QSV_E_ARG, "shots must be >= 0");
+    if (shots > 0 && (!uniforms || !out)) return fail(QSV_E_ARG, "uniforms or out is null");
+    if (m < 1 || m > n) return fail(QSV_E_ARG, "m must be in [1, n]");
+    bool identity = (m == n);
+    if (qubits) {
+        for (int j = 0; j < m; ++j) {
+            if (qubits[j] < 0 || qubits[j] >= n) return fail(QSV_E_ARG, "qubit out of range");
+            for (int i = 0; i < j; ++i)
+                if (qubits[i] == qubits[j]) return fail(QSV_E_ARG, "repeated qubit");
+            if (qubits[j] != j) identity = false;
+        }
+    } else if (m != n) {
+        return fail(QSV_E_ARG, "qubits == NULL measures all n qubits (m must be n)");
+    }
+    for (long long i = 0; i < shots; ++i)
+        if (!(uniforms[i] >= 0.0 && uniforms[i] < 1.0)) return fail(QSV_E_ARG, "uniforms must lie in [0, 1)");
+    if (!identity && m > 26) return fail(QSV_E_UNSUPPORTED, "marginal sampling over more than 26 qubits");
+    if (shots == 0) return QSV_OK;
+    DeviceGuard g(s->device);
+
+    // the distribution: the state itself (all qubits in order) or an FP64 marginal table
+    DevBuf table;
+    const void* src = s->buf;
+    int sdt = s->dtype;
+    if (!identity) {
+        if (!table.alloc(sizeof(double) << m)) return fail(QSV_E_OOM, "sampling table allocation failed");
+        if ((st = qsv_probs(s, qubits, m, table.p, 1)) != QSV_OK) return st;
+        src = table.p;
+        sdt = 2;
+    }
+    const int cb = std::min(m, kSampleChunkBits);
+    const long long nchunks = 1ll << (m - cb);
+
+    // chunk totals -> host prefix sums (sequential, FP64)
+    DevBuf dtot;
+    if (!dtot.alloc(sizeof(double) * nchunks)) return fail(QSV_E_OOM, "sampling buffer allocation failed");
+    std::vector<double> S(nchunks), Cp(nchunks + 1, 0.0);
+    QSV_HIP(launch_chunk_totals(sdt, src, cb, nchunks, (double*)dtot.p, s->stream));
+    QSV_HIP(hipMemcpyAsync(S.data(), dtot.p, sizeof(double) * nchunks, hipMemcpyDeviceToHost, s->stream));
+    QSV_HIP(hipStreamSynchronize(s->stream));
+    long long lastnz = -1;
+    for (long long c = 0; c < nchunks; ++c) {
+        Cp[c + 1] = Cp[c] + S[c];
+        if (S[c] > 0) lastnz = c;
+    }
+    const double P = Cp[nchunks];
+    if (lastnz < 0 || !(P > 0)) return fail(QSV_E_ARG, "the state has no probability mass");
+
+    // shots in increasing order of u; each goes to the chunk whose prefix interval holds
+    // u * P, with its residual inside that chunk
+    std::vector<long long> order(shots);
+    for (long long i = 0; i < shots; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](long long a, long long b) { return uniforms[a] < uniforms[b]; });
+    std::vector<double> res(shots);
+    std::vector<SampleChunk> list;
+    long long c = 0;
+    while (c < lastnz && S[c] <= 0) ++c;
+    for (long long k = 0; k < shots; ++k) {
+        const double t = uniforms[order[k]] * P;
+        while (c < lastnz && (t >= Cp[c + 1] || S[c] <= 0)) ++c;
+        res[k] = t - Cp[c];
+        if (list.empty() || list.back().chunk != c) list.push_back(SampleChunk{c, k, k + 1});
+        else list.back().hi = k + 1;
+    }
+    DevBuf dlist, dres, dout;
+    if (!dlist.alloc(sizeof(SampleChunk) * list.size()) || !dres.alloc(sizeof(double) * shots) ||
+        !dout.alloc(sizeof(long long) * shots))
+        return fail(QSV_E_OOM, "sampling buffer allocation failed");
+    std::vector<long long> got(shots);
+    QSV_HIP(hipMemcpyAsync(dlist.p, list.data(), sizeof(SampleChunk) * list.size(), hipMemcpyHostToDevice,
+                           s->stream));
+    QSV_HIP(hipMemcpyAsync(dres.p, res.data(), sizeof(double) * shots, hipMemcpyHostToDevice, s->stream));
+    QSV_HIP(launch_sample_chunks(sdt, src, cb, (const SampleChunk*)dlist.p, (long long)list.size(),
+                                 (const double*)dres.p, (long long*)dout.p, s->stream));
+    QSV_HIP(hipMemcpyAsync(got.data(), dout.p, sizeof(long long) * shots, hipMemcpyDeviceToHost, s->stream));
+    QSV_HIP(hipStreamSynchronize(s->stream));
+    for (long long k = 0; k < shots; ++k) out[order[k]] = got[k];
+    return QSV_OK;
+}
+
 qsv_status qsv_adjoint_grad(int n, qsv_dtype dtype, const qsv_op* ops, size_t n_ops, const double* params, int B,
                             int P, const qsv_pauli_term* H, size_t n_terms, double* energy, double* grad,
                             void* stream)

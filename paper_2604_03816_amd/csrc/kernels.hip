@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 #include <type_traits>
 
 #include "qsv_internal.h"
@@ -43,6 +44,14 @@ template <typename R> struct CT;
 template <> struct CT<float> { using T = float2; };
 template <> struct CT<double> { using T = double2; };
 
+// 16-byte register types for bulk moves (native vectors, so that arrays of them stay
+// in registers): two complex64 or one complex128 amplitude.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex2 __attribute__((ext_vector_type(2)));
+template <typename C> struct Lane16;
+template <> struct Lane16<float2> { using T = floatx4; };
+template <> struct Lane16<double2> { using T = doublex2; };
+
 template <typename C>
 __device__ __forceinline__ C cmul(C a, C b)
 {
@@ -61,12 +70,18 @@ __device__ __forceinline__ void cmac(C& acc, C a, C b)
     acc.y = fma(a.y, b.x, acc.y);
 }
 
+// PassArgs' arrays are indexed with compile-time indices only (fully unrolled loops
+// with a uniform guard): a runtime index into a kernel argument becomes a vector load
+// plus a wait on every outstanding memory operation, stores and prefetches included.
 __device__ __forceinline__ long long tile_base(const PassArgs& a, long long t)
 {
     long long base = 0;
-    for (int i = 0; i < a.nruns; ++i) {
-        base |= (t & ((1ll << a.run_len[i]) - 1)) << a.run_pos[i];
-        t >>= a.run_len[i];
+#pragma unroll
+    for (int i = 0; i < kMaxRuns; ++i) {
+        if (i < a.nruns) {
+            base |= (t & ((1ll << a.run_len[i]) - 1)) << a.run_pos[i];
+            t >>= a.run_len[i];
+        }
     }
     return base;
 }
@@ -75,32 +90,41 @@ __device__ __forceinline__ long long tile_base(const PassArgs& a, long long t)
 __device__ __forceinline__ long long local_off_bits(const PassArgs& a, int e, int lo, int hi)
 {
     long long o = 0;
-    for (int i = lo; i < hi; ++i) {
-        if ((e >> i) & 1) o += (i < a.L) ? (1ll << i) : (1ll << a.hbit[i - a.L]);
+#pragma unroll
+    for (int i = 0; i < kMaxTileQubits; ++i) {
+        if (i >= lo && i < hi && ((e >> i) & 1)) o += 1ll << a.phys[i];
     }
     return o;
 }
 
-// Move a tile between HBM and LDS.  Local index e = 256 * slice + tid: the bits below 8
-// come from the thread id (offset computed once per thread), the bits above from the
-// slice number; with the slice count NS a compile-time constant every slice's offset
-// is a sum of uniform strides (scalar ALU) and all NS loads of a thread are issued
-// back to back before the first is consumed.
+// Move a tile between HBM and LDS.  Every lane moves 16 bytes at a time: W = 1
+// complex128 or W = 2 adjacent complex64 amplitudes (local bit 0 is qubit 0, so such a
+// pair is contiguous in HBM).  Local index e = W (256 * slice + tid) + w: the bits from
+// the thread id give an offset computed once per thread, the bits above from the slice
+// number; with the slice count NS a compile-time constant every slice's offset is a sum
+// of uniform strides (scalar ALU) and all NS accesses of a thread are issued back to
+// back before the first is consumed.
 __device__ __forceinline__ long long local_stride(const PassArgs& a, int i)
 {
-    return (i < a.L) ? (1ll << i) : (1ll << a.hbit[i - a.L]);
+    return 1ll << a.phys[i];   // i is a compile-time constant at every call site
 }
 
-template <typename C, bool LOAD, int NS>
+template <typename C, bool LOAD, int NS, int W>
 __device__ __forceinline__ void move_tile_n(gptr<C> __restrict__ st, C* __restrict__ lds, const PassArgs& a,
                                             long long toff)
 {
+    static_assert(W == 1 || (W == 2 && sizeof(C) == 8), "16-byte lanes");
+    using V = typename std::conditional<W == 2, floatx4, C>::type;
+    constexpr int LW = W == 2 ? 1 : 0;
     constexpr int LB = NS >= 32 ? 5 : NS >= 16 ? 4 : NS >= 8 ? 3 : NS >= 4 ? 2 : NS >= 2 ? 1 : 0;
     long long hs[LB > 0 ? LB : 1];
 #pragma unroll
-    for (int b = 0; b < LB; ++b) hs[b] = local_stride(a, kLogThreads + b);
+    for (int b = 0; b < LB; ++b) hs[b] = local_stride(a, kLogThreads + LW + b);
     const int tid = threadIdx.x;
-    C v[NS];
+    V v[NS];
+    V* l = reinterpret_cast<V*>(lds);
+    // 16-byte unit u = 256 j + tid holds tile elements W u .. W u + W - 1
+    auto unit = [&](int j) { return (j << kLogThreads) + tid; };
     if (LOAD) {
 #pragma unroll
         for (int j = 0; j < NS; ++j) {
@@ -108,20 +132,20 @@ __device__ __forceinline__ void move_tile_n(gptr<C> __restrict__ st, C* __restri
 #pragma unroll
             for (int b = 0; b < LB; ++b)
                 if ((j >> b) & 1) so += hs[b];
-            v[j] = st[toff + so];
+            v[j] = *(gptr<V>)(st + toff + so);
         }
 #pragma unroll
-        for (int j = 0; j < NS; ++j) lds[(j << kLogThreads) + tid] = v[j];
+        for (int j = 0; j < NS; ++j) l[unit(j)] = v[j];
     } else {
 #pragma unroll
-        for (int j = 0; j < NS; ++j) v[j] = lds[(j << kLogThreads) + tid];
+        for (int j = 0; j < NS; ++j) v[j] = l[unit(j)];
 #pragma unroll
         for (int j = 0; j < NS; ++j) {
             long long so = 0;
 #pragma unroll
             for (int b = 0; b < LB; ++b)
                 if ((j >> b) & 1) so += hs[b];
-            st[toff + so] = v[j];
+            *(gptr<V>)(st + toff + so) = v[j];
         }
     }
 }
@@ -131,15 +155,29 @@ __device__ __forceinline__ void move_tile(gptr<C> __restrict__ st, C* __restrict
                                           long long base)
 {
     const int tid = threadIdx.x;
+    if constexpr (sizeof(C) == 8) {
+        // complex64 pairs whenever qubit 0 is a tile qubit and a slice is full
+        if (a.L >= 1 && a.m > kLogThreads) {
+            const long long toff = base + local_off_bits(a, tid << 1, 1, kLogThreads + 1);
+            switch (a.m - kLogThreads - 1) {
+            case 0: move_tile_n<C, LOAD, 1, 2>(st, lds, a, toff); break;
+            case 1: move_tile_n<C, LOAD, 2, 2>(st, lds, a, toff); break;
+            case 2: move_tile_n<C, LOAD, 4, 2>(st, lds, a, toff); break;
+            case 3: move_tile_n<C, LOAD, 8, 2>(st, lds, a, toff); break;
+            default: move_tile_n<C, LOAD, 16, 2>(st, lds, a, toff); break;
+            }
+            return;
+        }
+    }
     const int lowb = a.m < kLogThreads ? a.m : kLogThreads;
     const long long toff = base + local_off_bits(a, tid, 0, lowb);
     switch (a.m - kLogThreads) {
-    case 0: move_tile_n<C, LOAD, 1>(st, lds, a, toff); break;
-    case 1: move_tile_n<C, LOAD, 2>(st, lds, a, toff); break;
-    case 2: move_tile_n<C, LOAD, 4>(st, lds, a, toff); break;
-    case 3: move_tile_n<C, LOAD, 8>(st, lds, a, toff); break;
-    case 4: move_tile_n<C, LOAD, 16>(st, lds, a, toff); break;
-    case 5: move_tile_n<C, LOAD, 32>(st, lds, a, toff); break;
+    case 0: move_tile_n<C, LOAD, 1, 1>(st, lds, a, toff); break;
+    case 1: move_tile_n<C, LOAD, 2, 1>(st, lds, a, toff); break;
+    case 2: move_tile_n<C, LOAD, 4, 1>(st, lds, a, toff); break;
+    case 3: move_tile_n<C, LOAD, 8, 1>(st, lds, a, toff); break;
+    case 4: move_tile_n<C, LOAD, 16, 1>(st, lds, a, toff); break;
+    case 5: move_tile_n<C, LOAD, 32, 1>(st, lds, a, toff); break;
     default:   // tiles smaller than one slice (whole states below 256 amplitudes)
         if (tid < (1 << a.m)) {
             if (LOAD) lds[tid] = st[toff];
@@ -160,7 +198,10 @@ __device__ __forceinline__ int row_off(int r, const DevOp& op)
     return o;
 }
 
-// Group g of an op: insert a zero bit at each target position (ascending).
+// Group g of an op: insert a zero bit at each target position (ascending).  The map is
+// linear over XOR, so group_base(g0 + tid) = group_base(g0) ^ group_base(tid) when g0 is
+// a multiple of the workgroup size: a per-thread part computed once per op and a
+// uniform part per iteration.
 template <int K>
 __device__ __forceinline__ int group_base(int g, const DevOp& op)
 {
@@ -178,22 +219,24 @@ __device__ void op_dense(C* __restrict__ lds, int T, const DevOp& op, cptr<C> __
 {
     constexpr int D = 1 << K;
     const int G = T >> K;
-    for (int g = threadIdx.x; g < G; g += kThreads) {
-        const int b = group_base<K>(g, op);
+    const int bt = group_base<K>(threadIdx.x, op);
+    for (int g0 = 0; g0 < G; g0 += kThreads) {
+        if (g0 + (int)threadIdx.x >= G) break;
+        // b = group_base(g0) | group_base(tid): the uniform part is scalar work
+        const int b = group_base<K>(g0, op) | bt;
         C v[D];
 #pragma unroll
-        for (int r = 0; r < D; ++r) v[r] = lds[b + row_off<K>(r, op)];
+        for (int r = 0; r < D; ++r) v[r] = lds[b | row_off<K>(r, op)];
         // rows are not unrolled for wide gates: the row's matrix entries are uniform
         // (scalar) loads, the inputs stay in registers
         constexpr int RU = K <= 2 ? D : 1;
 #pragma unroll RU
         for (int r = 0; r < D; ++r) {
             C acc;
-            acc.x = 0;
-            acc.y = 0;
+            acc.x = acc.y = 0;
 #pragma unroll
             for (int c = 0; c < D; ++c) cmac(acc, M[r * D + c], v[c]);
-            lds[b + row_off<K>(r, op)] = acc;
+            lds[b | row_off<K>(r, op)] = acc;
         }
     }
 }
@@ -206,8 +249,6 @@ __device__ void op_dense(C* __restrict__ lds, int T, const DevOp& op, cptr<C> __
 // 8 rb + 2 q and 8 rb + 2 q + 1 of row block rb.  The A operands (host-arranged, see
 // the planner; staged in LDS once per kernel) stay in registers for the whole op.  All reads of a block precede its
 // writes, so the update is in place; waves own disjoint groups.
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-
 template <int K>
 __device__ void op_dense_mfma(float2* __restrict__ lds, int T, const DevOp& op, const float* __restrict__ A)
 {
@@ -219,15 +260,25 @@ __device__ void op_dense_mfma(float2* __restrict__ lds, int T, const DevOp& op, 
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) a[rb][ks] = A[(rb * KS + ks) * 64 + lane];
+    // this lane's row offsets (the same for every block)
+    int rin[KS / 2], rout[2 * RB];
+#pragma unroll
+    for (int j = 0; j < KS / 2; ++j) rin[j] = row_off<K>(4 * j + q, op);
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+        rout[2 * rb] = row_off<K>(8 * rb + 2 * q, op);
+        rout[2 * rb + 1] = row_off<K>(8 * rb + 2 * q + 1, op);
+    }
     const int nblk = (T >> K) >> 4;
+    const int bcol = group_base<K>(col, op);
     for (int blk = wave; blk < nblk; blk += kThreads / 64) {
-        const int b = group_base<K>((blk << 4) + col, op);
+        const int sb = group_base<K>(blk << 4, op) | bcol;
         floatx4 acc[RB];
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) acc[rb] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int j = 0; j < KS / 2; ++j) {
-            const float2 v = lds[b + row_off<K>(4 * j + q, op)];
+            const float2 v = lds[sb | rin[j]];
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) {
                 acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][2 * j], v.x, acc[rb], 0, 0, 0);
@@ -236,8 +287,8 @@ __device__ void op_dense_mfma(float2* __restrict__ lds, int T, const DevOp& op, 
         }
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
-            lds[b + row_off<K>(8 * rb + 2 * q, op)] = make_float2(acc[rb][0], acc[rb][1]);
-            lds[b + row_off<K>(8 * rb + 2 * q + 1, op)] = make_float2(acc[rb][2], acc[rb][3]);
+            lds[sb | rout[2 * rb]] = make_float2(acc[rb][0], acc[rb][1]);
+            lds[sb | rout[2 * rb + 1]] = make_float2(acc[rb][2], acc[rb][3]);
         }
     }
 }
@@ -249,19 +300,23 @@ __device__ void op_perm(C* __restrict__ lds, int T, const DevOp& op, cptr<C> __r
     constexpr int D = 1 << K;
     const int G = T >> K;
     const bool phased = op.flags != 0;
-    for (int g = threadIdx.x; g < G; g += kThreads) {
-        const int b = group_base<K>(g, op);
+    const int bt = group_base<K>(threadIdx.x, op);
+    for (int g0 = 0; g0 < G; g0 += kThreads) {
+        if (g0 + (int)threadIdx.x >= G) break;
+        const int b = group_base<K>(g0, op) | bt;
         C v[D];
 #pragma unroll
-        for (int r = 0; r < D; ++r) v[r] = lds[b + row_off<K>(src[r], op)];
+        for (int r = 0; r < D; ++r) v[r] = lds[b | row_off<K>(src[r], op)];
 #pragma unroll
-        for (int r = 0; r < D; ++r) lds[b + row_off<K>(r, op)] = phased ? cmul(ph[r], v[r]) : v[r];
+        for (int r = 0; r < D; ++r) lds[b | row_off<K>(r, op)] = phased ? cmul(ph[r], v[r]) : v[r];
     }
 }
 
-template <typename C>
-__device__ void op_diag(C* __restrict__ lds, int T, const DevOp& op, cptr<C> __restrict__ Dg,
-                        long long base)
+// Diagonal op: the table (2^k phases) is read from LDS when the planner staged it there
+// (per-lane indices; a global read here would also wait on every outstanding memory
+// operation of the pass), else from the plan pool.
+template <typename C, typename P>
+__device__ __forceinline__ void op_diag(C* __restrict__ lds, int T, const DevOp& op, P Dg, long long base)
 {
     // targets outside the tile contribute a per-tile constant part of the table index
     int gfix = 0, lp[kMaxDiagK];
@@ -290,11 +345,10 @@ __device__ __forceinline__ void apply_ops(C* __restrict__ lds, int T, cptr<DevOp
         if constexpr (std::is_same<C, float2>::value) {
             if (op.kind == OP_DENSE && op.aoff >= 0) {
                 const float* Am = alds + op.aoff;
-                switch (op.k) {
-                case 3: op_dense_mfma<3>(lds, T, op, Am); break;
-                case 4: op_dense_mfma<4>(lds, T, op, Am); break;
-                default: op_dense_mfma<5>(lds, T, op, Am); break;
-                }
+                // the planner gives matrix cores 3- and 4-qubit ops only (a 5-qubit
+                // operand block exceeds the per-pass LDS operand budget)
+                if (op.k == 3) op_dense_mfma<3>(lds, T, op, Am);
+                else op_dense_mfma<4>(lds, T, op, Am);
                 __syncthreads();
                 continue;
             }
@@ -316,6 +370,8 @@ __device__ __forceinline__ void apply_ops(C* __restrict__ lds, int T, cptr<DevOp
             case 4: op_perm<C, 4>(lds, T, op, M, S); break;
             default: op_perm<C, 5>(lds, T, op, M, S); break;
             }
+        } else if (op.aoff >= 0) {
+            op_diag<C>(lds, T, op, reinterpret_cast<const C*>(alds + op.aoff), base);
         } else {
             op_diag<C>(lds, T, op, M, base);
         }
@@ -345,7 +401,7 @@ __device__ __forceinline__ void run_tile(gptr<C> __restrict__ st, C* __restrict_
 }
 
 template <typename C>
-__global__ __launch_bounds__(kThreads) void k_pass(C* __restrict__ st, const PassArgs a,
+__global__ __launch_bounds__(kThreads) void k_pass(C* __restrict__ st, const PassArgs a, long long ntiles,
                                                    const DevOp* __restrict__ ops,
                                                    const C* __restrict__ pool,
                                                    const int* __restrict__ ipool,
@@ -356,7 +412,10 @@ __global__ __launch_bounds__(kThreads) void k_pass(C* __restrict__ st, const Pas
     float* alds = reinterpret_cast<float*>(smem + (sizeof(C) << a.m));
     stage_operands(alds, (cptr<float>)apool, a);
     __syncthreads();
-    run_tile<C>((gptr<C>)st, lds, a, blockIdx.x, (cptr<DevOp>)ops, (cptr<C>)pool, (cptr<int>)ipool, alds);
+    for (long long t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        run_tile<C>((gptr<C>)st, lds, a, t, (cptr<DevOp>)ops, (cptr<C>)pool, (cptr<int>)ipool, alds);
+        __syncthreads();
+    }
 }
 
 // Batched pass for continuous batching: one launch advances many independent states,
@@ -401,28 +460,14 @@ __global__ __launch_bounds__(kThreads) void k_batch_pass(const BatchItem* __rest
     }
 }
 
-template <typename C>
-__global__ __launch_bounds__(kThreads) void k_zero(C* __restrict__ st, long long N)
+// Fill with 16-byte stores: every chunk is `rest` except chunk 0, which is `first`
+// (|0...0> has amplitude 1 at index 0).  The state's byte size is a multiple of 16.
+__global__ __launch_bounds__(kThreads) void k_fill16(uint4* __restrict__ st, long long nchunks, uint4 first,
+                                                     uint4 rest)
 {
     const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
-        C z;
-        z.x = 0;
-        z.y = 0;
-        st[i] = z;
-    }
-}
-
-template <typename C>
-__global__ __launch_bounds__(kThreads) void k_init_zero(C* __restrict__ st, long long N)
-{
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
-        C z;
-        z.x = (i == 0) ? 1 : 0;
-        z.y = 0;
-        st[i] = z;
-    }
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nchunks; i += stride)
+        st[i] = (i == 0) ? first : rest;
 }
 
 // ------------------------------------------------------------------ reductions
@@ -469,18 +514,40 @@ __device__ NSum block_reduce(NSum v, NSum* scratch)
     return r;
 }
 
-template <typename C>
-__global__ __launch_bounds__(kThreads) void k_norm(const C* __restrict__ st, long long N,
+// Squared norm: 16-byte loads (two complex64 or one complex128 amplitude per chunk),
+// eight independent loads in flight per thread; each group of eight |a|^2 (FP64,
+// exact for FP32 inputs) is summed pairwise and added to a Neumaier pair.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_norm(const float4* __restrict__ st, long long nchunks,
                                                    double* __restrict__ partial)
 {
     __shared__ NSum scratch[kThreads / 64];
+    constexpr int U = 8;
     NSum a = {0.0, 0.0};
     const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
-        const C v = st[i];
-        const double x = v.x, y = v.y;
-        nadd(a, x * x + y * y);
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    auto sq = [](float4 v) -> double {
+        if constexpr (sizeof(R) == 4) {
+            return ((double)v.x * v.x + (double)v.y * v.y) + ((double)v.z * v.z + (double)v.w * v.w);
+        } else {
+            const double2 d = *reinterpret_cast<const double2*>(&v);
+            return d.x * d.x + d.y * d.y;
+        }
+    };
+    for (; i + (U - 1) * stride < nchunks; i += U * stride) {
+        float4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = st[i + u * stride];
+        double p[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) p[u] = sq(v[u]);
+#pragma unroll
+        for (int h = 1; h < U; h <<= 1)
+#pragma unroll
+            for (int u = 0; u < U; u += 2 * h) p[u] += p[u + h];
+        nadd(a, p[0]);
     }
+    for (; i < nchunks; i += stride) nadd(a, sq(st[i]));
     const NSum r = block_reduce(a, scratch);
     if (threadIdx.x == 0) {
         partial[2 * blockIdx.x] = r.s;
@@ -713,6 +780,104 @@ __global__ __launch_bounds__(kThreads) void k_pauli_apply(const C* __restrict__ 
     }
 }
 
+// ------------------------------------------------------------------ sampling
+
+// Probability of entry i: |alpha_i|^2 in FP64 (state sources) or a table entry.
+template <int SRC>
+__device__ __forceinline__ double prob_at(const void* src, long long i)
+{
+    if constexpr (SRC == 0) {
+        const float2 v = reinterpret_cast<const float2*>(src)[i];
+        return (double)v.x * v.x + (double)v.y * v.y;
+    } else if constexpr (SRC == 1) {
+        const double2 v = reinterpret_cast<const double2*>(src)[i];
+        return v.x * v.x + v.y * v.y;
+    } else {
+        return reinterpret_cast<const double*>(src)[i];
+    }
+}
+
+// Inclusive prefix sums of one chunk (2^cb entries, cb <= 12) into scan[] in LDS, in a
+// fixed order: each thread sums its run of E consecutive entries sequentially, the
+// thread totals are scanned within each wave (shuffles) and across the four waves.
+// Every chunk, in both sampling kernels, goes through this one function, so a chunk's
+// total and its last prefix sum are the same number.
+template <int SRC>
+__device__ void chunk_scan(const void* src, long long chunk, int cb, double* scan, double* wsum)
+{
+    const int size = 1 << cb;
+    const int E = size > kThreads ? size / kThreads : 1;
+    const int tid = threadIdx.x;
+    const long long base = chunk << cb;
+    double run = 0.0;
+    const bool mine = tid * E < size;
+    if (mine) {
+        for (int i = 0; i < E; ++i) {
+            run += prob_at<SRC>(src, base + tid * E + i);
+            scan[tid * E + i] = run;   // prefix within the thread's run
+        }
+    }
+    // inclusive scan of the thread totals: within the wave, then across waves
+    double x = mine ? run : 0.0;
+    const int lane = tid & 63, w = tid >> 6;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const double y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    double woff = 0.0;
+    for (int i = 0; i < w; ++i) woff += wsum[i];
+    const double off = woff + x - (mine ? run : 0.0);   // exclusive offset of this thread
+    if (mine) {
+        for (int i = 0; i < E; ++i) scan[tid * E + i] += off;
+    }
+    __syncthreads();
+}
+
+template <int SRC>
+__global__ __launch_bounds__(kThreads) void k_chunk_totals(const void* __restrict__ src, int cb,
+                                                           double* __restrict__ totals)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    double* scan = reinterpret_cast<double*>(smem);
+    __shared__ double wsum[kThreads / 64];
+    chunk_scan<SRC>(src, blockIdx.x, cb, scan, wsum);
+    if (threadIdx.x == 0) totals[blockIdx.x] = scan[(1 << cb) - 1];
+}
+
+// One workgroup per listed chunk: rebuild the chunk's prefix sums, then every shot of
+// the chunk finds the smallest k with residual < scan[k] (binary search).  Residuals
+// are clamped into [0, total) first: below zero (rounding) picks the first entry of
+// nonzero probability, at or above the total picks the last one.
+template <int SRC>
+__global__ __launch_bounds__(kThreads) void k_sample_chunks(const void* __restrict__ src, int cb,
+                                                            const SampleChunk* __restrict__ list,
+                                                            const double* __restrict__ residual,
+                                                            long long* __restrict__ outcome)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    double* scan = reinterpret_cast<double*>(smem);
+    __shared__ double wsum[kThreads / 64];
+    const SampleChunk c = list[blockIdx.x];
+    chunk_scan<SRC>(src, c.chunk, cb, scan, wsum);
+    const int size = 1 << cb;
+    const double total = scan[size - 1];
+    const double below = nextafter(total, 0.0);
+    for (long long i = c.lo + threadIdx.x; i < c.hi; i += kThreads) {
+        double r = residual[i];
+        r = r < 0.0 ? 0.0 : (r >= total ? below : r);
+        int lo = 0, hi = size - 1;   // smallest k with r < scan[k]; scan[size - 1] > r
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (r < scan[mid]) hi = mid;
+            else lo = mid + 1;
+        }
+        outcome[i] = (c.chunk << cb) + lo;
+    }
+}
+
 template <typename C, typename R>
 __global__ __launch_bounds__(kThreads) void k_probs_full(const C* __restrict__ st, long long N,
                                                          R* __restrict__ out)
@@ -824,7 +989,8 @@ hipError_t launch_zsum_batch(int dtype, const ZItem* items, const int* count, do
     return hipGetLastError();
 }
 
-// One workgroup per tile.
+// One workgroup per tile (the hardware keeps as many resident as registers and LDS
+// allow; a finished workgroup's slot is refilled at once).
 template <typename R>
 hipError_t launch_pass_t(void* st, const PassArgs& a, long long ntiles, const DevOp* ops, const void* pool,
                          const int* ipool, const float* apool, hipStream_t s)
@@ -837,8 +1003,8 @@ hipError_t launch_pass_t(void* st, const PassArgs& a, long long ntiles, const De
         attr_set = true;
     }
     const size_t lds = (sizeof(C) << a.m) + sizeof(float) * (size_t)a.a_len;
-    hipLaunchKernelGGL(k_pass<C>, dim3((unsigned)ntiles), dim3(kThreads), lds, s, (C*)st, a, ops, (const C*)pool,
-                       ipool, apool);
+    hipLaunchKernelGGL(k_pass<C>, dim3((unsigned)ntiles), dim3(kThreads), lds, s, (C*)st, a, ntiles, ops,
+                       (const C*)pool, ipool, apool);
     return hipGetLastError();
 }
 
@@ -876,24 +1042,32 @@ hipError_t launch_pass(int dtype, void* st, const PassArgs& a, long long ntiles,
                       : launch_pass_t<double>(st, a, ntiles, ops, pool, ipool, apool, s);
 }
 
+static hipError_t launch_fill16(void* st, long long bytes, uint4 first, uint4 rest, hipStream_t s)
+{
+    const long long nchunks = bytes / 16;
+    const long long blocks = std::min<long long>((nchunks + kThreads - 1) / kThreads, 8192);
+    hipLaunchKernelGGL(k_fill16, dim3((unsigned)blocks), dim3(kThreads), 0, s, (uint4*)st, nchunks, first, rest);
+    return hipGetLastError();
+}
+
 hipError_t launch_init_zero(int dtype, void* st, long long N, hipStream_t s)
 {
-    const long long blocks = std::min<long long>((N + kThreads - 1) / kThreads, 8192);
-    if (dtype == 0)
-        hipLaunchKernelGGL(k_init_zero<float2>, dim3((unsigned)blocks), dim3(kThreads), 0, s, (float2*)st, N);
-    else
-        hipLaunchKernelGGL(k_init_zero<double2>, dim3((unsigned)blocks), dim3(kThreads), 0, s, (double2*)st, N);
-    return hipGetLastError();
+    const uint4 zero = make_uint4(0, 0, 0, 0);
+    uint4 one = zero;
+    if (dtype == 0) {
+        const float f = 1.0f;
+        memcpy(&one.x, &f, 4);
+    } else {
+        const double d = 1.0;
+        memcpy(&one.x, &d, 8);
+    }
+    return launch_fill16(st, N * (dtype == 0 ? 8 : 16), one, zero, s);
 }
 
 hipError_t launch_zero(int dtype, void* st, long long N, hipStream_t s)
 {
-    const long long blocks = std::min<long long>((N + kThreads - 1) / kThreads, 8192);
-    if (dtype == 0)
-        hipLaunchKernelGGL(k_zero<float2>, dim3((unsigned)blocks), dim3(kThreads), 0, s, (float2*)st, N);
-    else
-        hipLaunchKernelGGL(k_zero<double2>, dim3((unsigned)blocks), dim3(kThreads), 0, s, (double2*)st, N);
-    return hipGetLastError();
+    const uint4 zero = make_uint4(0, 0, 0, 0);
+    return launch_fill16(st, N * (dtype == 0 ? 8 : 16), zero, zero, s);
 }
 
 int norm_grid(long long N)
@@ -903,10 +1077,11 @@ int norm_grid(long long N)
 
 hipError_t launch_norm(int dtype, const void* st, long long N, double* partial, int grid, hipStream_t s)
 {
+    const long long nchunks = N * (dtype == 0 ? 8 : 16) / 16;
     if (dtype == 0)
-        hipLaunchKernelGGL(k_norm<float2>, dim3(grid), dim3(kThreads), 0, s, (const float2*)st, N, partial);
+        hipLaunchKernelGGL(k_norm<float>, dim3(grid), dim3(kThreads), 0, s, (const float4*)st, nchunks, partial);
     else
-        hipLaunchKernelGGL(k_norm<double2>, dim3(grid), dim3(kThreads), 0, s, (const double2*)st, N, partial);
+        hipLaunchKernelGGL(k_norm<double>, dim3(grid), dim3(kThreads), 0, s, (const float4*)st, nchunks, partial);
     return hipGetLastError();
 }
 
@@ -981,6 +1156,27 @@ hipError_t launch_probs_marg(int dtype, const void* st, const MargArgs& a, doubl
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sum_chunks, dim3((unsigned)((M + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
                        (const double*)partial, M, a.nchunks, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_chunk_totals(int src_dtype, const void* src, int chunk_bits, long long nchunks, double* totals,
+                               hipStream_t s)
+{
+    if (chunk_bits > kSampleChunkBits || nchunks <= 0) return hipErrorInvalidValue;
+    const size_t lds = sizeof(double) << chunk_bits;
+    auto k = src_dtype == 0 ? k_chunk_totals<0> : src_dtype == 1 ? k_chunk_totals<1> : k_chunk_totals<2>;
+    hipLaunchKernelGGL(k, dim3((unsigned)nchunks), dim3(kThreads), lds, s, src, chunk_bits, totals);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample_chunks(int src_dtype, const void* src, int chunk_bits, const SampleChunk* list,
+                                long long nlist, const double* residual, long long* outcome, hipStream_t s)
+{
+    if (chunk_bits > kSampleChunkBits) return hipErrorInvalidValue;
+    if (nlist <= 0) return hipSuccess;
+    const size_t lds = sizeof(double) << chunk_bits;
+    auto k = src_dtype == 0 ? k_sample_chunks<0> : src_dtype == 1 ? k_sample_chunks<1> : k_sample_chunks<2>;
+    hipLaunchKernelGGL(k, dim3((unsigned)nlist), dim3(kThreads), lds, s, src, chunk_bits, list, residual, outcome);
     return hipGetLastError();
 }
 

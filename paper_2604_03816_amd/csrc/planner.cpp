@@ -35,6 +35,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <queue>
 
 namespace qsv {
@@ -59,6 +60,28 @@ PlanOpts default_opts(int dtype)
         o.sigma = 8;
     }
     return o;
+}
+
+bool plan_opts_from(int dtype, const qsv_plan_opts* pub, PlanOpts& o, std::string& err)
+{
+    o = default_opts(dtype);
+    if (!pub) return true;
+    if (pub->fuse < 0 || pub->fuse > 2) { err = "fuse must be 0, 1 or 2"; return false; }
+    o.fuse = pub->fuse;
+    if (pub->kmax) o.kmax = pub->kmax;
+    if (pub->cost_aware) o.cost_aware = pub->cost_aware;
+    if (pub->tile_qubits) o.tile_qubits = pub->tile_qubits;
+    if (pub->low_qubits) o.low_qubits = pub->low_qubits;
+    if (pub->pass_budget != 0) o.pass_budget = pub->pass_budget;
+    if (pub->matrix_cores) {
+        if (pub->matrix_cores != -1 && (pub->matrix_cores < 3 || pub->matrix_cores > kMaxK)) {
+            err = "matrix_cores must be 0, -1 or in [3, 5]";
+            return false;
+        }
+        o.mfma_min_k = pub->matrix_cores < 0 ? 0 : pub->matrix_cores;
+    }
+    if (o.fuse == 0) o.max_ops_per_pass = 1;
+    return true;
 }
 
 int classify(const std::vector<cd>& m, int k)
@@ -420,7 +443,7 @@ bool make_plan(int n, int dtype, const std::vector<InGate>& gates, const PlanOpt
     }
 
     // ---- Algorithm 2
-    if (o.fuse) run_fusion(nodes, o);
+    if (o.fuse == 1) run_fusion(nodes, o);
     for (const int v : topo_order(nodes))
         if (!is_identity(nodes[v].g)) P.fused.push_back(nodes[v].g);
 
@@ -482,7 +505,7 @@ bool make_plan(int n, int dtype, const std::vector<InGate>& gates, const PlanOpt
         PassArgs a{};
         a.m = (int)pp.active.size();
         a.L = pp.low;
-        for (int i = a.L; i < a.m; ++i) a.hbit[i - a.L] = (unsigned char)pp.active[i];
+        for (int i = 0; i < a.m; ++i) a.phys[i] = (unsigned char)pp.active[i];
         a.nruns = 0;
         {
             unsigned long long A = 0;
@@ -531,6 +554,28 @@ bool make_plan(int n, int dtype, const std::vector<InGate>& gates, const PlanOpt
             } else if (g.kind == OP_DIAG) {
                 for (int r = 0; r < dd; ++r) P.pool.push_back(g.m[(size_t)r * dd + r]);
                 ++P.diag_ops;
+                // the table also goes to LDS (per-lane lookups stay on chip): the entries
+                // in the state's precision as raw floats, 16-byte aligned
+                const int per = dtype == 0 ? 2 : 4;
+                const int at = (a.a_len + 3) & ~3;
+                if (at + per * dd <= o.mfma_lds_floats) {
+                    P.apool.resize((size_t)a.a_off + at, 0.0f);
+                    for (int r = 0; r < dd; ++r) {
+                        const cd v = g.m[(size_t)r * dd + r];
+                        if (dtype == 0) {
+                            P.apool.push_back((float)v.real());
+                            P.apool.push_back((float)v.imag());
+                        } else {
+                            const double re = v.real(), im = v.imag();
+                            float w[4];
+                            std::memcpy(w, &re, 8);
+                            std::memcpy(w + 2, &im, 8);
+                            P.apool.insert(P.apool.end(), w, w + 4);
+                        }
+                    }
+                    d.aoff = at;
+                    a.a_len = at + per * dd;
+                }
             } else {
                 d.ioff = (int)P.ipool.size();
                 d.flags = 0;

@@ -5,6 +5,7 @@
 #include <string>
 #include <vector>
 
+#include "../../include/qsv.h"
 #include "qsv_internal.h"
 
 namespace qsv {
@@ -40,7 +41,8 @@ struct PlanOpts {
     double sigma = 8;          // per-op on-chip cost in FMA-per-amplitude units
     int max_ops_per_pass = 0;  // 0: no limit
     int mfma_min_k = 0;        // dense ops with k >= this run on MFMA (complex64 only); 0: never
-    int mfma_lds_floats = 2048;  // per-pass cap of MFMA operand floats staged in LDS
+    int mfma_lds_floats = 2048;  // per-pass cap of operand floats staged in LDS (MFMA matrices,
+                                 // diagonal tables)
 };
 
 struct PassPlan {
@@ -69,6 +71,13 @@ struct HostPlan {
     double fma_per_amp = 0, mfma_fma_per_amp = 0;
 };
 
+// Planner defaults for a dtype (QSV_C64 / QSV_C128).
+PlanOpts default_opts(int dtype);
+
+// Defaults overridden by the caller's public options (NULL: defaults only); checks the
+// public ranges.  Returns false with a message on a bad value.
+bool plan_opts_from(int dtype, const qsv_plan_opts* pub, PlanOpts& o, std::string& err);
+
 // Arithmetic of one op, in FMA per amplitude (dense 4*2^k, diagonal 4, permutation 0
 // or 4 with phases).
 double op_fma(const FGate& g);
@@ -84,8 +93,5 @@ int classify(const std::vector<cd>& m, int k);
 // Runs fusion (when o.fuse) and pass scheduling; fills every field of `out`.
 bool make_plan(int n, int dtype, const std::vector<InGate>& gates, const PlanOpts& o,
                HostPlan& out, std::string& err);
-
-// Default options for a dtype (0 = complex64, 1 = complex128).
-PlanOpts default_opts(int dtype);
 
 }  // namespace qsv

@@ -25,15 +25,17 @@ struct DevOp {
     int off;            // offset into the complex pool: dense 4^k, diagonal 2^k, permutation 2^k phases
     int ioff;           // permutation: offset into the int pool (2^k source rows)
     int flags;          // permutation: 1 when some phase differs from 1
-    int aoff;           // complex64 dense op on MFMA: float offset of its real-embedded matrix (MFMA
-                        // operand order) inside the pass's operand block in LDS, else -1
+    int aoff;           // float offset inside the pass's operand block in LDS, else -1: a complex64
+                        // dense op on MFMA (its real-embedded matrix in MFMA operand order) or a
+                        // diagonal op (its 2^k phases, bit copies of the pool entries)
 };
 
 // Everything a pass kernel needs to place its tile in the state vector.
-// Local tile index bits 0..L-1 are physical bits 0..L-1; local bits L..m-1 are the
-// other tile qubits in ascending order, at physical bits hbit[].  The tile number is
+// Local tile index bit i sits at physical bit phys[i]: bits 0..L-1 are physical bits
+// 0..L-1, bits L..m-1 the other tile qubits in ascending order.  The tile number is
 // deposited into the remaining (free) physical bits, which form nruns maximal runs
-// (run_pos, run_len).  Kept small (bytes) so the kernels hold it in scalar registers.
+// (run_pos, run_len).  Kept small (bytes); kernels index the arrays only with
+// compile-time indices, so every read is a scalar load.
 constexpr int kMaxRuns = kMaxTileQubits + 2;
 struct PassArgs {
     int m;
@@ -43,7 +45,7 @@ struct PassArgs {
     int nruns;
     int a_off;          // the pass's MFMA operand block: float offset in the plan's operand array
     int a_len;          // and its length in floats (staged into LDS behind the tile)
-    unsigned char hbit[kMaxTileQubits];
+    unsigned char phys[kMaxTileQubits];
     unsigned char run_pos[kMaxRuns];
     unsigned char run_len[kMaxRuns];
 };
@@ -129,6 +131,20 @@ hipError_t launch_expval(int dtype, const void* sa, const void* sb, const PassAr
 hipError_t launch_pauli_apply(int dtype, const void* in, void* out, long long N, const PauliSumArgs& p,
                               int accumulate, hipStream_t s);
 hipError_t launch_probs_full(int dtype, const void* st, long long N, void* out, hipStream_t s);
+
+// Sampling: the distribution is either |alpha|^2 of a state (src_dtype 0 / 1) or an FP64
+// table (src_dtype 2), cut into chunks of 2^chunk_bits entries.  launch_chunk_totals
+// writes each chunk's total; launch_sample_chunks resolves the shots of the listed chunks
+// (chunk id, shot range [lo, hi) into the sorted residual / outcome arrays).
+constexpr int kSampleChunkBits = 12;
+struct SampleChunk {
+    long long chunk;
+    long long lo, hi;
+};
+hipError_t launch_chunk_totals(int src_dtype, const void* src, int chunk_bits, long long nchunks, double* totals,
+                               hipStream_t s);
+hipError_t launch_sample_chunks(int src_dtype, const void* src, int chunk_bits, const SampleChunk* list,
+                                long long nlist, const double* residual, long long* outcome, hipStream_t s);
 hipError_t launch_probs_marg(int dtype, const void* st, const MargArgs& a, double* partial, double* out,
                              hipStream_t s);
 

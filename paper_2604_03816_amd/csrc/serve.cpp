@@ -453,16 +453,8 @@ qsv_status qsv_server_submit(qsv_server s, int n, qsv_dtype dtype, const qsv_gat
     auto r = std::make_shared<Req>();
     r->n = n;
     r->dtype = dtype;
-    r->popts = default_opts(dtype);
-    if (popts) {
-        r->popts.fuse = popts->fuse;
-        if (popts->kmax) r->popts.kmax = popts->kmax;
-        if (popts->cost_aware) r->popts.cost_aware = popts->cost_aware;
-        if (popts->tile_qubits) r->popts.tile_qubits = popts->tile_qubits;
-        if (popts->low_qubits) r->popts.low_qubits = popts->low_qubits;
-        if (popts->pass_budget != 0) r->popts.pass_budget = popts->pass_budget;
-        if (!r->popts.fuse) r->popts.max_ops_per_pass = 1;
-    }
+    std::string oerr;
+    if (!plan_opts_from(dtype, popts, r->popts, oerr)) return set_error(QSV_E_ARG, oerr);
     // served tiles are capped so every batched launch needs at most 32 KiB of LDS per
     // workgroup (several workgroups per CU)
     const int cap = kServeTileQubits[dtype];

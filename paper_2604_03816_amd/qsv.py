@@ -37,7 +37,7 @@ class Gate(ctypes.Structure):
 class PlanOpts(ctypes.Structure):
     _fields_ = [("fuse", ctypes.c_int), ("kmax", ctypes.c_int), ("cost_aware", ctypes.c_int),
                 ("tile_qubits", ctypes.c_int), ("low_qubits", ctypes.c_int),
-                ("pass_budget", ctypes.c_double)]
+                ("pass_budget", ctypes.c_double), ("matrix_cores", ctypes.c_int)]
 
 
 class PlanStats(ctypes.Structure):
@@ -64,7 +64,7 @@ EXPORTS = [
     "qsv_last_error", "qsv_version", "qsv_alloc", "qsv_free", "qsv_reset", "qsv_info", "qsv_get_state",
     "qsv_set_state", "qsv_gate_matrix", "qsv_plan_create", "qsv_plan_free", "qsv_plan_get_stats",
     "qsv_plan_fused_gate", "qsv_plan_pass_info", "qsv_plan_pass_ops", "qsv_plan_emulate", "qsv_plan_apply", "qsv_plan_apply_range",
-    "qsv_apply_fused", "qsv_sync", "qsv_norm", "qsv_expval_pauli", "qsv_probs", "qsv_adjoint_grad",
+    "qsv_apply_fused", "qsv_sync", "qsv_norm", "qsv_expval_pauli", "qsv_probs", "qsv_sample", "qsv_adjoint_grad",
     "qsv_server_create", "qsv_server_free", "qsv_server_submit", "qsv_server_step", "qsv_server_results",
     "qsv_server_get_stats", "qsv_server_get_state", "qsv_server_release",
 ]
@@ -104,6 +104,8 @@ def lib():
     L.qsv_norm.argtypes = [vp, dp]
     L.qsv_expval_pauli.argtypes = [vp, ctypes.POINTER(PauliTerm), sz, dp, dp]
     L.qsv_probs.argtypes = [vp, ctypes.POINTER(i), i, vp, i]
+    L.qsv_sample.argtypes = [vp, ctypes.POINTER(i), i, ctypes.POINTER(ctypes.c_double), ctypes.c_longlong,
+                             ctypes.POINTER(ctypes.c_longlong)]
     L.qsv_adjoint_grad.argtypes = [i, i, ctypes.POINTER(COp), sz, dp, i, i, ctypes.POINTER(PauliTerm), sz,
                                    dp, dp, vp]
     _LIB = L
@@ -215,9 +217,14 @@ class ArrayGateList:
         self.arr = a.ctypes.data_as(ctypes.POINTER(Gate))
 
 
-def _opts(fuse=True, kmax=0, cost_aware=0, tile_qubits=0, low_qubits=0, pass_budget=0.0) -> PlanOpts:
+def _opts(fuse=True, kmax=0, cost_aware=0, tile_qubits=0, low_qubits=0, pass_budget=0.0,
+          matrix_cores=0) -> PlanOpts:
+    """fuse: True/1 DAG fusion, False/0 plain (one gate per pass), 2 = no fusion but
+    gates share passes; matrix_cores: complex64 dense ops on >= this many targets use
+    MFMA (0 default, -1 never)."""
     o = PlanOpts()
-    o.fuse = 1 if fuse else 0
+    o.fuse = int(fuse) if not isinstance(fuse, bool) else (1 if fuse else 0)
+    o.matrix_cores = matrix_cores
     o.kmax = kmax
     o.cost_aware = cost_aware
     o.tile_qubits = tile_qubits
@@ -390,6 +397,21 @@ class State:
         host = np.empty(1 << m, dtype=rdt)
         check(lib().qsv_probs(self.h, qp, m, host.ctypes.data_as(ctypes.c_void_p), 0))
         return host
+
+    def sample(self, uniforms, qubits: Optional[Sequence[int]] = None) -> np.ndarray:
+        """One computational-basis outcome per uniform in [0, 1) (inverse transform of the
+        Born distribution over ``qubits``, bit j <-> qubits[j]; None = all qubits)."""
+        u = np.ascontiguousarray(uniforms, dtype=np.float64).ravel()
+        out = np.empty(u.size, dtype=np.int64)
+        if qubits is None:
+            m, qp = self.n, None
+        else:
+            m = len(qubits)
+            qa = (ctypes.c_int * m)(*[int(q) for q in qubits])
+            qp = ctypes.cast(qa, ctypes.POINTER(ctypes.c_int))
+        check(lib().qsv_sample(self.h, qp, m, u.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), u.size,
+                               out.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong))))
+        return out
 
     def free(self):
         if getattr(self, "h", None):

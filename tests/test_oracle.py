@@ -338,3 +338,58 @@ def test_memory_arithmetic_from_the_paper():
     assert (2 ** 28) * 16 // gib == golden("state_bytes_28q_c128_gib")
     assert int(math.floor(math.log2(24 * gib / 16))) == golden("max_qubits_24gib_c128")
     assert int(math.floor(math.log2(24 * gib / 8))) == golden("max_qubits_24gib_c64")
+
+
+# ------------------------------------------------------------------ sampling (Eq. 1 Born rule)
+
+def test_sampling_ghz_closed_form():
+    n = 5
+    psi = oracle.simulate(n, C.ghz(n))
+    u = np.array([0.0, 0.25, 0.49, 0.51, 0.75, 0.999999])
+    assert list(oracle.sample(psi, range(n), u)) == [0, 0, 0, 31, 31, 31]
+    # marginal over two qubits of GHZ: outcomes 00 or 11 only
+    assert set(oracle.sample(psi, [3, 1], np.linspace(0, 0.99, 50)).tolist()) == {0, 3}
+
+
+def test_sampling_brute_force_inverse_cdf():
+    rng = np.random.default_rng(11)
+    n = 4
+    v = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+    v[5] = 0   # a zero-probability outcome is never drawn
+    psi = np.ascontiguousarray(v)   # deliberately unnormalised
+    for qubits in ([0, 1, 2, 3], [2, 0], [3]):
+        p = np.zeros(1 << len(qubits))
+        for k in range(1 << n):
+            o = sum(((k >> q) & 1) << j for j, q in enumerate(qubits))
+            p[o] += abs(psi[k]) ** 2
+        u = rng.random(500)
+        got = oracle.sample(psi, qubits, u)
+        for ui, g in zip(u, got):
+            t, acc, want = ui * p.sum(), 0.0, None
+            for k in range(len(p)):
+                acc += p[k]
+                if t < acc:
+                    want = k
+                    break
+            assert want is not None and g == want and p[g] > 0
+    with pytest.raises(ValueError):
+        oracle.sample(psi, [0], np.array([1.0]))
+
+
+def test_sampling_frequencies_and_bit_order():
+    rng = np.random.default_rng(12)
+    n = 4
+    th = rng.uniform(0.2, 1.3, n)
+    # product state: qubit q is cos(th_q)|0> + sin(th_q)|1>
+    psi = np.ones(1)
+    for q in range(n):
+        psi = np.kron(np.array([np.cos(th[q]), np.sin(th[q])]), psi)
+    psi = np.ascontiguousarray(psi.astype(np.complex128))
+    qubits = [2, 0]
+    p1 = {q: np.sin(th[q]) ** 2 for q in qubits}
+    expect = np.array([(p1[2] if o & 1 else 1 - p1[2]) * (p1[0] if o & 2 else 1 - p1[0]) for o in range(4)])
+    shots = 200000
+    got = oracle.sample(psi, qubits, rng.random(shots))
+    freq = np.bincount(got, minlength=4) / shots
+    sigma = np.sqrt(expect * (1 - expect) / shots)
+    assert np.all(np.abs(freq - expect) < 5 * sigma)

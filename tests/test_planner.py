@@ -86,6 +86,17 @@ def test_null_arguments_return_errors():
     assert L.qsv_free(None) == qsv.QSV_OK
 
 
+def test_adopted_buffer_checks_come_before_any_device_call():
+    # buffers are checked on the host: too small, or not 16-byte aligned (the kernels
+    # move 16 bytes per lane); neither pointer is ever dereferenced
+    L = qsv.lib()
+    out = ctypes.c_void_p()
+    assert L.qsv_alloc(10, 0, ctypes.c_void_p(0x10000), 4096, None, ctypes.byref(out)) == qsv.QSV_E_ARG
+    assert L.qsv_alloc(10, 0, ctypes.c_void_p(0x10008), 8192, None, ctypes.byref(out)) == qsv.QSV_E_ARG
+    assert "aligned" in L.qsv_last_error().decode()
+    assert out.value is None
+
+
 # ------------------------------------------------------------------ fusion soundness (Eq. 9 / Eq. 10)
 
 def _random_gate_circuit(n, count, rng, kmax_gate=3):
@@ -220,6 +231,26 @@ def test_wide_gates_in_narrow_tiles():
         qsv.Plan(n, "c64", ops, tile_qubits=5, low_qubits=2)
 
 
+def test_fusion_modes_and_matrix_core_option():
+    n = 16
+    ops = C.brickwork(n, 12, 9)
+    plain = qsv.Plan(n, "c64", ops, fuse=False).stats()
+    grouped = qsv.Plan(n, "c64", ops, fuse=2).stats()
+    fused = qsv.Plan(n, "c64", ops).stats()
+    # mode 2 keeps every gate (minus exact identities) but shares passes
+    assert grouped["fused_out"] == plain["fused_out"] == plain["passes"]
+    assert grouped["passes"] < plain["passes"]
+    assert fused["fused_out"] < grouped["fused_out"]
+    assert grouped["fma_per_amp"] == pytest.approx(plain["fma_per_amp"])
+    assert fused["mfma_ops"] > 0 and fused["mfma_fma_per_amp"] > 0
+    no_mc = qsv.Plan(n, "c64", ops, matrix_cores=-1).stats()
+    assert no_mc["mfma_ops"] == 0 and no_mc["mfma_fma_per_amp"] == 0
+    assert qsv.Plan(n, "c128", ops).stats()["mfma_ops"] == 0   # complex128 never uses them
+    for bad in ({"fuse": 3}, {"fuse": -1}, {"matrix_cores": 2}, {"matrix_cores": 6}, {"matrix_cores": -2}):
+        with pytest.raises(qsv.QSVError):
+            qsv.Plan(n, "c64", ops, **bad)
+
+
 # ------------------------------------------------------------------ device tables (host re-enactment)
 
 @pytest.mark.parametrize("seed", range(8))
@@ -236,7 +267,8 @@ def test_device_tables_reproduce_the_circuit(seed, tq, lq):
     v = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
     psi0 = np.ascontiguousarray(v / np.linalg.norm(v))
     ref = oracle.simulate(n, ops, psi=psi0.copy())
-    for opts in ({}, {"fuse": False}, {"cost_aware": -1}, {"kmax": 1}, {"pass_budget": -1}):
+    for opts in ({}, {"fuse": False}, {"fuse": 2}, {"cost_aware": -1}, {"kmax": 1}, {"pass_budget": -1},
+                 {"matrix_cores": -1}, {"matrix_cores": 5}):
         dt = "c64" if (seed % 2 or tq == 13) else "c128"   # 13-qubit tiles fit LDS only in complex64
         plan = qsv.Plan(n, dt, ops, tile_qubits=tq, low_qubits=lq, **opts)
         got = plan.emulate(psi0)
