@@ -66,6 +66,14 @@ struct qsv_state_s {
     size_t work_bytes = 0;
     double* h_work = nullptr;
     size_t hwork_bytes = 0;
+    // plan-table arena for one-shot applications: pinned staging + device block, both
+    // grow-only; tab_ev marks the end of the last copy out of the staging block
+    unsigned char* h_tab = nullptr;
+    size_t htab_bytes = 0;
+    unsigned char* d_tab = nullptr;
+    size_t dtab_bytes = 0;
+    hipEvent_t tab_ev = nullptr;
+    bool tab_ev_pending = false;
 };
 
 struct qsv_plan_s {
@@ -160,6 +168,22 @@ bool read_gate_public(const qsv_gate& g, int n, InGate& out, std::string& err) {
 
 namespace {
 
+// The plan's complex pool in the state's precision (matrices rounded once from FP64).
+void pack_pool(const HostPlan& hp, unsigned char* dst)
+{
+    for (size_t i = 0; i < hp.pool.size(); ++i) {
+        if (hp.dtype == QSV_C64) {
+            float* f = reinterpret_cast<float*>(dst) + 2 * i;
+            f[0] = (float)hp.pool[i].real();
+            f[1] = (float)hp.pool[i].imag();
+        } else {
+            double* f = reinterpret_cast<double*>(dst) + 2 * i;
+            f[0] = hp.pool[i].real();
+            f[1] = hp.pool[i].imag();
+        }
+    }
+}
+
 qsv_status upload_plan(qsv_plan p, int device)
 {
     if (p->device == device) return QSV_OK;
@@ -197,17 +221,7 @@ qsv_status upload_plan(qsv_plan p, int device)
         return fail(QSV_E_OOM, "plan table allocation failed");
     }
     std::vector<unsigned char> pool(npool * eb, 0);
-    for (size_t i = 0; i < hp.pool.size(); ++i) {
-        if (hp.dtype == QSV_C64) {
-            float* f = reinterpret_cast<float*>(pool.data()) + 2 * i;
-            f[0] = (float)hp.pool[i].real();
-            f[1] = (float)hp.pool[i].imag();
-        } else {
-            double* f = reinterpret_cast<double*>(pool.data()) + 2 * i;
-            f[0] = hp.pool[i].real();
-            f[1] = hp.pool[i].imag();
-        }
-    }
+    pack_pool(hp, pool.data());
     if (!hp.ops.empty()) QSV_HIP(hipMemcpy(p->d_ops, hp.ops.data(), hp.ops.size() * sizeof(DevOp), hipMemcpyHostToDevice));
     QSV_HIP(hipMemcpy(p->d_pool, pool.data(), pool.size(), hipMemcpyHostToDevice));
     if (!hp.ipool.empty()) QSV_HIP(hipMemcpy(p->d_ipool, hp.ipool.data(), hp.ipool.size() * sizeof(int), hipMemcpyHostToDevice));
@@ -275,24 +289,36 @@ PassArgs tile_args(int n, int m, int L, unsigned long long need, std::vector<int
     return a;
 }
 
-// out[i] = Re <a|P_i|b> (imag == false) or Im <a|P_i|b> (imag == true), unweighted, for
-// states a and b of s's shape (a == b for expectation values).  Terms are grouped so
-// that each group's X/Y supports fit one tile; one read pass per group.
-qsv_status pauli_elements(qsv_state s, const void* sa, const void* sb, const std::vector<PTerm>& terms, bool imag,
-                          std::vector<double>& out)
+// Pauli matrix elements Re <a|P_i|b> (imag == false) or Im <a|P_i|b> (imag == true),
+// unweighted, for states a and b of one shape (a == b for expectation values), in three
+// steps: plan_elements groups the terms so that each group's X/Y supports fit one tile
+// (one read pass per group) and lays out the per-workgroup partials; launch_elements
+// enqueues the passes; combine_elements adds each term's partials (fixed order,
+// compensated) once they are on the host.
+struct ElemGroup {
+    PassArgs a;
+    TermArgs ta;
+    long long ntiles;
+    int grid;
+    std::vector<int> idx;   // term indices
+    size_t off;             // first double of this group's partials
+};
+
+bool plan_elements(int n, const std::vector<PTerm>& terms, bool imag, std::vector<ElemGroup>& G, size_t& doubles,
+                   std::string& err, int dtype)
 {
-    const int n = s->n;
-    const PlanOpts o = default_opts(s->dtype);
+    const PlanOpts o = default_opts(dtype);
     const int m = std::min(n, kExpvalMaxTileQubits);
     const int L = std::min(o.low_qubits, m);
     const unsigned long long lowmask = (L >= 64) ? ~0ull : ((1ull << L) - 1);
-    out.assign(terms.size(), 0.0);
     std::vector<std::vector<int>> groups;
     std::vector<unsigned long long> gneed;
     for (size_t i = 0; i < terms.size(); ++i) {
         const unsigned long long x = terms[i].x;
-        if (__builtin_popcountll(x | lowmask) > m)
-            return fail(QSV_E_UNSUPPORTED, "Pauli term flips more qubits than one tile holds");
+        if (__builtin_popcountll(x | lowmask) > m) {
+            err = "Pauli term flips more qubits than one tile holds";
+            return false;
+        }
         bool placed = false;
         for (size_t g = 0; g < groups.size() && !placed; ++g) {
             const unsigned long long need = gneed[g] | x;
@@ -307,44 +333,78 @@ qsv_status pauli_elements(qsv_state s, const void* sa, const void* sb, const std
             gneed.push_back(x);
         }
     }
+    G.clear();
+    doubles = 0;
     for (size_t g = 0; g < groups.size(); ++g) {
         std::vector<int> active;
-        const PassArgs a = tile_args(n, m, L, gneed[g], active);
-        TermArgs ta{};
-        ta.nterms = (int)groups[g].size();
-        for (int i = 0; i < ta.nterms; ++i) {
+        ElemGroup E;
+        E.a = tile_args(n, m, L, gneed[g], active);
+        E.ta = TermArgs{};
+        E.ta.nterms = (int)groups[g].size();
+        for (int i = 0; i < E.ta.nterms; ++i) {
             const PTerm& p = terms[groups[g][i]];
             int xl = 0, zl = 0;
             unsigned long long zg = p.z;
-            for (int j = 0; j < a.m; ++j) {
+            for (int j = 0; j < E.a.m; ++j) {
                 const unsigned long long b = 1ull << active[j];
                 if (p.x & b) xl |= 1 << j;
                 if (p.z & b) { zl |= 1 << j; zg &= ~b; }
             }
-            ta.xloc[i] = xl;
-            ta.zloc[i] = zl;
-            ta.zglob[i] = (long long)zg;
-            ta.ny[i] = p.ny + (imag ? 3 : 0);   // Im z = Re(-i z), and -i = i^3
+            E.ta.xloc[i] = xl;
+            E.ta.zloc[i] = zl;
+            E.ta.zglob[i] = (long long)zg;
+            E.ta.ny[i] = p.ny + (imag ? 3 : 0);   // Im z = Re(-i z), and -i = i^3
         }
-        const long long ntiles = 1ll << (n - a.m);
-        const int grid = (int)std::min<long long>(ntiles, 1024);
-        const size_t bytes = (size_t)grid * ta.nterms * 2 * sizeof(double);
-        qsv_status st = ensure_work(s, bytes);
-        if (st != QSV_OK) return st;
-        st = ensure_hwork(s, bytes);
-        if (st != QSV_OK) return st;
-        QSV_HIP(launch_expval(s->dtype, sa, sb, a, ta, ntiles, grid, s->d_work, s->stream));
-        QSV_HIP(hipMemcpyAsync(s->h_work, s->d_work, bytes, hipMemcpyDeviceToHost, s->stream));
-        QSV_HIP(hipStreamSynchronize(s->stream));
-        for (int i = 0; i < ta.nterms; ++i) {
+        E.ntiles = 1ll << (n - E.a.m);
+        E.grid = (int)std::min<long long>(E.ntiles, 1024);
+        E.idx = groups[g];
+        E.off = doubles;
+        doubles += (size_t)E.grid * E.ta.nterms * 2;
+        G.push_back(std::move(E));
+    }
+    return true;
+}
+
+hipError_t launch_elements(int dtype, const void* sa, const void* sb, const std::vector<ElemGroup>& G,
+                           double* d_partial, hipStream_t stream)
+{
+    for (const ElemGroup& E : G) {
+        const hipError_t e = launch_expval(dtype, sa, sb, E.a, E.ta, E.ntiles, E.grid, d_partial + E.off, stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+void combine_elements(const std::vector<ElemGroup>& G, const double* h_partial, size_t nterms, std::vector<double>& out)
+{
+    out.assign(nterms, 0.0);
+    for (const ElemGroup& E : G) {
+        for (int i = 0; i < E.ta.nterms; ++i) {
             NS acc;
-            for (int b = 0; b < grid; ++b) {
-                acc.add(s->h_work[((size_t)b * ta.nterms + i) * 2]);
-                acc.c += s->h_work[((size_t)b * ta.nterms + i) * 2 + 1];
+            for (int b = 0; b < E.grid; ++b) {
+                acc.add(h_partial[E.off + ((size_t)b * E.ta.nterms + i) * 2]);
+                acc.c += h_partial[E.off + ((size_t)b * E.ta.nterms + i) * 2 + 1];
             }
-            out[groups[g][i]] = acc.value();
+            out[E.idx[i]] = acc.value();
         }
     }
+}
+
+qsv_status pauli_elements(qsv_state s, const void* sa, const void* sb, const std::vector<PTerm>& terms, bool imag,
+                          std::vector<double>& out)
+{
+    std::vector<ElemGroup> G;
+    size_t doubles = 0;
+    std::string err;
+    if (!plan_elements(s->n, terms, imag, G, doubles, err, s->dtype)) return fail(QSV_E_UNSUPPORTED, err);
+    const size_t bytes = std::max<size_t>(doubles, 1) * sizeof(double);
+    qsv_status st = ensure_work(s, bytes);
+    if (st != QSV_OK) return st;
+    if ((st = ensure_hwork(s, bytes)) != QSV_OK) return st;
+    QSV_HIP(launch_elements(s->dtype, sa, sb, G, s->d_work, s->stream));
+    QSV_HIP(hipMemcpyAsync(s->h_work, s->d_work, bytes, hipMemcpyDeviceToHost, s->stream));
+    QSV_HIP(hipStreamSynchronize(s->stream));
+    combine_elements(G, s->h_work, terms.size(), out);
     return QSV_OK;
 }
 
@@ -377,32 +437,69 @@ qsv_status pauli_sum_apply(qsv_state s, const void* src, void* dst, const std::v
 }
 
 // Plans and enqueues `gates` on a state (the plan is released after the stream drains).
+// Enqueues every pass of a host plan on the state's stream, its tables copied into the
+// state's arena: one asynchronous copy, no allocation once the arena is large enough,
+// no wait for the device (only for the previous copy out of the staging block).
+qsv_status enqueue_plan(qsv_state s, const HostPlan& hp)
+{
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t eb = elem_bytes(hp.dtype);
+    const size_t o_ops = 0;
+    const size_t o_pool = o_ops + al(hp.ops.size() * sizeof(DevOp));
+    const size_t o_ipool = o_pool + al(hp.pool.size() * eb);
+    const size_t o_apool = o_ipool + al(hp.ipool.size() * sizeof(int));
+    const size_t total = std::max<size_t>(o_apool + al(hp.apool.size() * sizeof(float)), 256);
+    if (s->tab_ev_pending) {
+        QSV_HIP(hipEventSynchronize(s->tab_ev));
+        s->tab_ev_pending = false;
+    }
+    if (!s->tab_ev) QSV_HIP(hipEventCreateWithFlags(&s->tab_ev, hipEventDisableTiming));
+    if (total > s->htab_bytes) {
+        if (s->h_tab) QSV_HIP(hipHostFree(s->h_tab));
+        s->h_tab = nullptr;
+        s->htab_bytes = 0;
+        const size_t want = std::max<size_t>(total * 2, 1 << 16);
+        QSV_HIP(hipHostMalloc((void**)&s->h_tab, want, hipHostMallocDefault));
+        s->htab_bytes = want;
+    }
+    if (total > s->dtab_bytes) {
+        if (s->d_tab) {
+            QSV_HIP(hipStreamSynchronize(s->stream));   // passes still reading the old block
+            QSV_HIP(hipFree(s->d_tab));
+        }
+        s->d_tab = nullptr;
+        s->dtab_bytes = 0;
+        const size_t want = std::max<size_t>(total * 2, 1 << 16);
+        if (hipMalloc((void**)&s->d_tab, want) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(QSV_E_OOM, "plan table allocation failed");
+        }
+        s->dtab_bytes = want;
+    }
+    unsigned char* h = s->h_tab;
+    if (!hp.ops.empty()) std::memcpy(h + o_ops, hp.ops.data(), hp.ops.size() * sizeof(DevOp));
+    pack_pool(hp, h + o_pool);
+    if (!hp.ipool.empty()) std::memcpy(h + o_ipool, hp.ipool.data(), hp.ipool.size() * sizeof(int));
+    if (!hp.apool.empty()) std::memcpy(h + o_apool, hp.apool.data(), hp.apool.size() * sizeof(float));
+    QSV_HIP(hipMemcpyAsync(s->d_tab, h, total, hipMemcpyHostToDevice, s->stream));
+    QSV_HIP(hipEventRecord(s->tab_ev, s->stream));
+    s->tab_ev_pending = true;
+    unsigned char* d = s->d_tab;
+    for (size_t i = 0; i < hp.passes.size(); ++i)
+        QSV_HIP(launch_pass(s->dtype, s->buf, hp.pargs[i], hp.pgrid[i], (const DevOp*)(d + o_ops), d + o_pool,
+                            (const int*)(d + o_ipool), (const float*)(d + o_apool), s->stream));
+    return QSV_OK;
+}
+
+// Plans (default options) and enqueues a gate list; asynchronous.
 qsv_status apply_gates(qsv_state s, const std::vector<InGate>& gates)
 {
     if (gates.empty()) return QSV_OK;
     PlanOpts o = default_opts(s->dtype);
-    qsv_plan p = new qsv_plan_s();
+    HostPlan hp;
     std::string err;
-    if (!make_plan(s->n, s->dtype, gates, o, p->hp, err)) {
-        delete p;
-        return fail(QSV_E_ARG, err);
-    }
-    qsv_status st = upload_plan(p, s->device);
-    for (size_t i = 0; st == QSV_OK && i < p->hp.passes.size(); ++i) {
-        const hipError_t e = launch_pass(s->dtype, s->buf, p->hp.pargs[i], p->hp.pgrid[i], p->d_ops, p->d_pool,
-                                         p->d_ipool, p->d_apool, s->stream);
-        if (e != hipSuccess) st = fail(QSV_E_DEVICE, std::string("pass: ") + hipGetErrorString(e));
-    }
-    const hipError_t e = hipStreamSynchronize(s->stream);
-    if (p->device >= 0) {
-        (void)hipFree(p->d_ops);
-        (void)hipFree(p->d_pool);
-        (void)hipFree(p->d_ipool);
-        (void)hipFree(p->d_apool);
-    }
-    delete p;
-    if (st == QSV_OK && e != hipSuccess) return fail(QSV_E_DEVICE, std::string("apply: ") + hipGetErrorString(e));
-    return st;
+    if (!make_plan(s->n, s->dtype, gates, o, hp, err)) return fail(QSV_E_ARG, err);
+    return enqueue_plan(s, hp);
 }
 
 }  // namespace
@@ -457,6 +554,9 @@ qsv_status qsv_free(qsv_state s)
     if (s->owned) (void)hipFree(s->buf);
     if (s->d_work) (void)hipFree(s->d_work);
     if (s->h_work) (void)hipHostFree(s->h_work);
+    if (s->d_tab) (void)hipFree(s->d_tab);
+    if (s->h_tab) (void)hipHostFree(s->h_tab);
+    if (s->tab_ev) (void)hipEventDestroy(s->tab_ev);
     delete s;
     return QSV_OK;
 }
@@ -764,9 +864,9 @@ qsv_status qsv_apply_fused(qsv_state s, const qsv_gate* gates, size_t n_gates, c
     st = qsv_plan_create(s->n, (qsv_dtype)s->dtype, gates, n_gates, opts, &p);
     if (st != QSV_OK) return st;
     if (stats) qsv_plan_get_stats(p, stats);
-    st = qsv_plan_apply(s, p);
     {
         DeviceGuard g(s->device);
+        st = enqueue_plan(s, p->hp);
         const hipError_t e = hipStreamSynchronize(s->stream);
         qsv_plan_free(p);
         if (st == QSV_OK && e != hipSuccess) return fail(QSV_E_DEVICE, std::string("apply: ") + hipGetErrorString(e));
@@ -1053,6 +1153,80 @@ qsv_status qsv_adjoint_grad(int n, qsv_dtype dtype, const qsv_op* ops, size_t n_
         return g;
     };
 
+    // The sweep's structure depends on the op kinds and targets only, not on the angles,
+    // so it is planned once.  The circuit still to be undone is kept as a list of op
+    // indices in time order.  Each step first undoes the fixed gates at its tail, then
+    // takes a layer: walking back from the tail, a rotation joins the layer when no op
+    // already passed over (a member or one left behind) touches its qubit.  An op left
+    // behind blocks its qubits for everything earlier, so it shares no qubit with any
+    // member that precedes it in time and commutes to before the whole layer; in that
+    // equivalent order the layer is contiguous at the tail, and all its gradients come
+    // from one evaluation at the current point.  The layer is then undone and leaves
+    // the list.
+    struct Layer {
+        std::vector<long long> fixed;   // fixed gates undone first (descending time)
+        std::vector<long long> ops;     // the layer's rotations (descending time)
+        std::vector<ElemGroup> G;
+    };
+    std::vector<Layer> layers;
+    size_t partial_doubles = 0;
+    {
+        std::vector<long long> rest(n_ops);
+        for (size_t i = 0; i < n_ops; ++i) rest[i] = (long long)i;
+        auto qubits_of = [&](long long i) {
+            unsigned long long q = 0;
+            if (ops[i].kind == 0) {
+                for (int j = 0; j < fixed[i].k; ++j) q |= 1ull << fixed[i].t[j];
+            } else {
+                q = 1ull << ops[i].targets[0];
+            }
+            return q;
+        };
+        std::vector<long long> trailing;
+        while (!rest.empty()) {
+            while (!rest.empty() && ops[rest.back()].kind == 0) {
+                trailing.push_back(rest.back());
+                rest.pop_back();
+            }
+            if (rest.empty()) break;
+            Layer Ly;
+            Ly.fixed.swap(trailing);
+            unsigned long long blocked = 0;
+            std::vector<char> take(rest.size(), 0);
+            const unsigned long long all = (n >= 64) ? ~0ull : ((1ull << n) - 1);
+            for (long long r = (long long)rest.size() - 1; r >= 0 && (blocked & all) != all; --r) {
+                const long long i = rest[(size_t)r];
+                const unsigned long long q = qubits_of(i);
+                if (ops[i].kind != 0 && !(blocked & q)) {
+                    take[(size_t)r] = 1;
+                    Ly.ops.push_back(i);
+                }
+                blocked |= q;
+            }
+            std::vector<long long> keep;
+            keep.reserve(rest.size());
+            for (size_t r = 0; r < rest.size(); ++r)
+                if (!take[r]) keep.push_back(rest[r]);
+            rest.swap(keep);
+            std::vector<PTerm> gterms(Ly.ops.size());
+            for (size_t l = 0; l < Ly.ops.size(); ++l) {
+                const qsv_op& o = ops[Ly.ops[l]];
+                const unsigned long long bit = 1ull << o.targets[0];
+                PTerm t;
+                if (o.kind == 1) t.x = bit;                               // X
+                else if (o.kind == 2) { t.x = bit; t.z = bit; t.ny = 1; }  // Y
+                else t.z = bit;                                            // Z
+                t.coeff = 1.0;
+                gterms[l] = t;
+            }
+            size_t d = 0;
+            if (!plan_elements(n, gterms, true, Ly.G, d, err, dtype)) return fail(QSV_E_UNSUPPORTED, err);
+            for (ElemGroup& E : Ly.G) E.off += partial_doubles;
+            partial_doubles += d;
+            layers.push_back(std::move(Ly));
+        }
+    }
+
     qsv_state phi = nullptr, lam = nullptr;
     qsv_status st = qsv_alloc(n, dtype, nullptr, 0, stream, &phi);
     if (st != QSV_OK) return st;
@@ -1061,6 +1235,10 @@ qsv_status qsv_adjoint_grad(int n, qsv_dtype dtype, const qsv_op* ops, size_t n_
         qsv_free(phi);
         return st;
     }
+    // every layer's partials for one parameter vector, read back once per vector
+    const size_t pbytes = std::max<size_t>(partial_doubles, 1) * sizeof(double);
+    if ((st = ensure_work(lam, pbytes)) == QSV_OK) st = ensure_hwork(lam, pbytes);
+    std::vector<double> gv;
     for (int b = 0; b < B && st == QSV_OK; ++b) {
         const double* th = params + (size_t)b * P;
         double* gb = grad + (size_t)b * P;
@@ -1078,47 +1256,38 @@ qsv_status qsv_adjoint_grad(int n, qsv_dtype dtype, const qsv_op* ops, size_t n_
         for (size_t t = 0; t < hterms.size(); ++t) e.add(hterms[t].coeff * hv[t]);
         energy[b] = e.value();
         if ((st = pauli_sum_apply(lam, phi->buf, lam->buf, hterms)) != QSV_OK) break;
-        // reverse sweep
+        // reverse sweep, asynchronous: uncompute (fixed gates and the previous layer,
+        // one plan applied to both states), then the layer's Im <lambda|P_j|phi>
         std::vector<InGate> pending;   // inverse gates still to apply, in application order
-        long long i = (long long)n_ops - 1;
-        while (i >= 0 && st == QSV_OK) {
-            if (ops[i].kind == 0) {
-                pending.push_back(op_gate((size_t)i, th, true));
-                --i;
-                continue;
-            }
-            // a layer: consecutive rotations (walking backwards) on distinct qubits
-            unsigned long long used = 0;
-            long long j = i;
-            std::vector<long long> layer;
-            while (j >= 0 && ops[j].kind != 0 && !((used >> ops[j].targets[0]) & 1)) {
-                used |= 1ull << ops[j].targets[0];
-                layer.push_back(j);
-                --j;
-            }
+        for (size_t li = 0; li < layers.size() && st == QSV_OK; ++li) {
+            const Layer& Ly = layers[li];
+            for (const long long k : Ly.fixed) pending.push_back(op_gate((size_t)k, th, true));
             if (!pending.empty()) {
-                if ((st = apply_gates(phi, pending)) != QSV_OK) break;
-                if ((st = apply_gates(lam, pending)) != QSV_OK) break;
+                HostPlan hp;
+                if (!make_plan(n, dtype, pending, default_opts(dtype), hp, err)) {
+                    st = fail(QSV_E_ARG, err);
+                    break;
+                }
+                if ((st = enqueue_plan(phi, hp)) != QSV_OK) break;
+                if ((st = enqueue_plan(lam, hp)) != QSV_OK) break;
                 pending.clear();
             }
-            std::vector<PTerm> gterms(layer.size());
-            for (size_t l = 0; l < layer.size(); ++l) {
-                const qsv_op& o = ops[layer[l]];
-                const unsigned long long bit = 1ull << o.targets[0];
-                PTerm t;
-                if (o.kind == 1) t.x = bit;                               // X
-                else if (o.kind == 2) { t.x = bit; t.z = bit; t.ny = 1; }  // Y
-                else t.z = bit;                                            // Z
-                t.coeff = 1.0;
-                gterms[l] = t;
+            const hipError_t he = launch_elements(dtype, lam->buf, phi->buf, Ly.G, lam->d_work, lam->stream);
+            if (he != hipSuccess) {
+                st = fail(QSV_E_DEVICE, std::string("adjoint: ") + hipGetErrorString(he));
+                break;
             }
-            std::vector<double> gv;
-            if ((st = pauli_elements(lam, lam->buf, phi->buf, gterms, true, gv)) != QSV_OK) break;
-            for (size_t l = 0; l < layer.size(); ++l) {
-                gb[ops[layer[l]].param] += gv[l];
-                pending.push_back(op_gate((size_t)layer[l], th, true));
-            }
-            i = j;
+            for (const long long k : Ly.ops) pending.push_back(op_gate((size_t)k, th, true));
+        }
+        if (st != QSV_OK) break;
+        if (hipMemcpyAsync(lam->h_work, lam->d_work, pbytes, hipMemcpyDeviceToHost, lam->stream) != hipSuccess ||
+            hipStreamSynchronize(lam->stream) != hipSuccess) {
+            st = fail(QSV_E_DEVICE, "adjoint: partials read-back failed");
+            break;
+        }
+        for (const Layer& Ly : layers) {
+            combine_elements(Ly.G, lam->h_work, Ly.ops.size(), gv);
+            for (size_t l = 0; l < Ly.ops.size(); ++l) gb[ops[Ly.ops[l]].param] += gv[l];
         }
     }
     qsv_free(phi);

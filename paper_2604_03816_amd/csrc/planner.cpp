@@ -49,14 +49,14 @@ PlanOpts default_opts(int dtype)
         o.tile_qubits = 12;
         o.low_qubits = 5;
         o.whole_state_max = 13;
-        o.pass_budget = 224;
+        o.pass_budget = 160;
         o.sigma = 8;
         o.mfma_min_k = 3;
     } else {            // complex128: 16-byte amplitudes
         o.tile_qubits = 12;
         o.low_qubits = 4;
         o.whole_state_max = 12;
-        o.pass_budget = 320;
+        o.pass_budget = 448;
         o.sigma = 8;
     }
     return o;
