@@ -29,7 +29,7 @@ cpu_baseline: the FP64 CPU oracle (gate by gate, all host threads) on the first 
 the same 30-qubit circuit, reported in the same unit with its own (unfused) gate count.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-c128]
-       [--no-serve] [--no-precision] [--no-adjoint] [--no-sampling] [--copy-probe]
+       [--no-serve] [--no-precision] [--no-adjoint] [--no-sampling] [--no-noise] [--copy-probe]
 """
 import argparse
 import json
@@ -65,6 +65,7 @@ def parse():
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-sampling", action="store_true")
+    ap.add_argument("--no-noise", action="store_true")
     ap.add_argument("--precision-qubits", type=int, nargs="*", default=[30, 32])
     ap.add_argument("--adjoint-qubits", type=int, default=24)
     ap.add_argument("--adjoint-batch", type=int, default=64)
@@ -356,6 +357,43 @@ def sampling_bench(args, ops):
     return out
 
 
+def noise_bench(args):
+    """Density-matrix noise study (Table 8's circuits: H on qubit 0, CNOT from qubit 0 to
+    every other qubit, single-qubit depolarizing p = 0.01 after every gate): exact F_cl
+    and TVD against the ideal distribution for Bell and GHZ-3..5, and the same circuit at
+    13 qubits (a 26-qubit vec(rho)) for timing; complex128."""
+    import numpy as np
+    import torch
+    from paper_2604_03816_amd import circuits as C
+    from paper_2604_03816_amd import qsv
+
+    def circuit(n, p=0.01):
+        ops = [C.Op("H", (0,)), C.Op("DEPOLARIZE", (0,), (p,))]
+        for t in range(1, n):
+            ops += [C.Op("CNOT", (0, t)), C.Op("DEPOLARIZE", (0,), (p,)), C.Op("DEPOLARIZE", (t,), (p,))]
+        return ops
+
+    out = []
+    for n in (2, 3, 4, 5, 13):
+        dm = qsv.DensityMatrix(n, "c128")
+        ops = circuit(n)
+        dm.apply(ops)
+        torch.cuda.synchronize()
+        dm.reset()
+        t0 = time.perf_counter()
+        dm.apply(ops)
+        p = dm.probs()
+        wall = time.perf_counter() - t0
+        ideal = np.zeros(1 << n)
+        ideal[0] = ideal[-1] = 0.5
+        fcl = float(np.sum(np.sqrt(ideal * np.clip(p, 0, None))) ** 2)
+        out.append({"n": n, "gates_and_channels": len(ops), "F_cl": fcl, "TVD": float(0.5 * np.abs(p - ideal).sum()),
+                    "apply_and_probs_ms": wall * 1e3})
+        dm.free()
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -410,6 +448,8 @@ def main():
         rec["adjoint"] = adjoint_bench(args)
     if not args.no_sampling:
         rec["sampling"] = sampling_bench(args, ops)
+    if not args.no_noise:
+        rec["noise"] = noise_bench(args)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(C, args, ops)
     print(json.dumps(rec))

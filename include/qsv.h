@@ -223,6 +223,41 @@ qsv_status qsv_probs(qsv_state s, const int* qubits, int m, void* out, int out_o
 qsv_status qsv_sample(qsv_state s, const int* qubits, int m, const double* uniforms, long long shots,
                       long long* out);
 
+/* ------------------------------------------------------------------ density matrices */
+
+/* A mixed state of n qubits (the noise study of Table 8) is held in an ordinary state of
+ * 2n qubits as vec(rho), entry rho[row, col] at index row + 2^n col; qsv_alloc(2n, ...)
+ * and qsv_reset give rho = |0...0><0...0|.  Then U rho U^dagger = (conj(U) (x) U) vec(rho):
+ * a gate U on targets T acts as U on T and conj(U) on T + n, and a channel with Kraus
+ * operators K_a acts as sum_a conj(K_a) (x) K_a on (T, T + n) -- ordinary (non-unitary)
+ * matrices for the same planner and kernels. */
+typedef struct {
+    int kind;            /* 0: unitary gate on k <= 5 targets (mat as in qsv_gate, not diagonal);
+                            1: depolarizing channel on k = 1 or 2 targets: each of the 4^k - 1
+                               non-identity Pauli strings with probability p / (4^k - 1);
+                            2: amplitude damping on k = 1 target with decay probability p */
+    int k;
+    int targets[5];      /* system qubits, < n */
+    const double* mat;   /* kind 0 only */
+    double p;            /* kinds 1, 2: in [0, 1] */
+} qsv_dm_op;
+
+/* Applies the ops in order to the density matrix held in s (s has 2n qubits), fused and
+ * scheduled like qsv_apply_fused (opts may be NULL).  Synchronous.  Errors: QSV_E_ARG
+ * (odd qubit count, bad op), QSV_E_OOM, QSV_E_DEVICE. */
+qsv_status qsv_dm_apply(qsv_state s, const qsv_dm_op* ops, size_t n_ops, const qsv_plan_opts* opts);
+
+/* Outcome probabilities of measuring `qubits` (m distinct system qubits; bit j of the
+ * outcome <-> qubits[j]; NULL = all n in order) on the density matrix: the marginal of
+ * its diagonal, FP64, written to host `out` (2^m doubles).  Synchronous. */
+qsv_status qsv_dm_probs(qsv_state s, const int* qubits, int m, double* out);
+
+/* Tr(rho P_t) for Pauli terms on the system qubits (FP64 per thread, compensated
+ * combination); per_term (host) receives coeff_t Tr(rho P_t), sum their total; either may
+ * be NULL.  Synchronous. */
+qsv_status qsv_dm_expval_pauli(qsv_state s, const qsv_pauli_term* terms, size_t n_terms, double* per_term,
+                               double* sum);
+
 /* ------------------------------------------------------------------ gradients */
 
 /* One op of a parameterised circuit.  kind 0: fixed gate (k, targets, mat as in

@@ -15,6 +15,8 @@ definitions that sit on top:
                               (the parameter-shift rule the paper's PennyLane path uses,
                               Section 7.4), evaluated with ``simulate`` + ``expval``
 * ``fd_grad``             -- central finite differences
+* ``dm_simulate``         -- density matrix of a circuit with noise channels (Kraus
+                              operators; depolarizing and amplitude damping), dense
 * ``sample``              -- computational-basis measurement sampling by inverse
                               transform of the Born probabilities (Eq. 1), the
                               backend's third operation (Section 4)
@@ -220,3 +222,96 @@ def fd_grad(n: int, template, params: Sequence[float], terms, h: float = 1e-6,
         e[j] = h
         g[j] = (energy(n, template, params + e, terms) - energy(n, template, params - e, terms)) / (2 * h)
     return g
+
+
+# ------------------------------------------------------------------ density matrices
+
+_PAULI = {"I": np.eye(2, dtype=complex), "X": np.array([[0, 1], [1, 0]], dtype=complex),
+          "Y": np.array([[0, -1j], [1j, 0]]), "Z": np.array([[1, 0], [0, -1]], dtype=complex)}
+
+
+def kraus_ops(op) -> List[np.ndarray]:
+    """Kraus operators of an op on its own qubits (local bit j <-> op.qubits[j]): a gate
+    is its single unitary; DEPOLARIZE(p) on k qubits is sqrt(1-p) I plus every
+    non-identity Pauli string times sqrt(p / (4^k - 1)); AMPDAMP(gamma) is
+    [[1, 0], [0, sqrt(1-gamma)]] and [[0, sqrt(gamma)], [0, 0]]."""
+    if op.name == "DEPOLARIZE":
+        k, p = len(op.qubits), float(op.params[0])
+        strings = [""]
+        for _ in range(k):
+            strings = [s + c for s in strings for c in "IXYZ"]
+        out = []
+        for s in strings:
+            m = np.ones((1, 1), dtype=complex)
+            for c in s:                       # first letter = local bit 0 (rightmost factor)
+                m = np.kron(_PAULI[c], m)
+            w = 1.0 - p if set(s) == {"I"} else p / (4 ** k - 1)
+            out.append(math.sqrt(w) * m)
+        return out
+    if op.name == "AMPDAMP":
+        g = float(op.params[0])
+        return [np.array([[1, 0], [0, math.sqrt(1 - g)]], dtype=complex),
+                np.array([[0, math.sqrt(g)], [0, 0]], dtype=complex)]
+    return [op_matrix(op)]
+
+
+def _embed(n: int, M: np.ndarray, targets: Sequence[int]) -> np.ndarray:
+    """The 2^n x 2^n operator of M on `targets` (identity elsewhere), column by column
+    through the gate-by-gate ``apply`` (which does not assume unitarity)."""
+    N = 1 << n
+    full = np.zeros((N, N), dtype=complex)
+    for j in range(N):
+        e = np.zeros(N, dtype=complex)
+        e[j] = 1.0
+        apply(e, M, targets)
+        full[:, j] = e
+    return full
+
+
+def dm_simulate(n: int, ops: Iterable, rho: np.ndarray = None) -> np.ndarray:
+    """rho -> sum_a K_a rho K_a^dagger for every op in order, from |0...0><0...0|."""
+    N = 1 << n
+    if rho is None:
+        rho = np.zeros((N, N), dtype=complex)
+        rho[0, 0] = 1.0
+    for op in ops:
+        ks = [_embed(n, K, op.qubits) for K in kraus_ops(op)]
+        rho = sum(K @ rho @ K.conj().T for K in ks)
+    return rho
+
+
+def dm_probs(rho: np.ndarray, qubits: Sequence[int]) -> np.ndarray:
+    """Marginal of the diagonal over `qubits` (bit j of the outcome <-> qubits[j])."""
+    n = int(rho.shape[0]).bit_length() - 1
+    d = np.real(np.diag(rho))
+    out = np.zeros(1 << len(qubits))
+    for k in range(1 << n):
+        o = sum(((k >> q) & 1) << j for j, q in enumerate(qubits))
+        out[o] += d[k]
+    return out
+
+
+def dm_expval(rho: np.ndarray, terms) -> float:
+    """sum_t coeff_t Tr(rho P_t), P_t as a dense Kronecker product."""
+    n = int(rho.shape[0]).bit_length() - 1
+    tot = 0.0
+    for c, string in terms:
+        letters = ["I"] * n
+        for q, p in string:
+            letters[q] = p
+        P = np.ones((1, 1), dtype=complex)
+        for q in range(n):
+            P = np.kron(_PAULI[letters[q]], P)
+        tot += c * float(np.real(np.trace(rho @ P)))
+    return tot
+
+
+def classical_fidelity(p: np.ndarray, q: np.ndarray) -> float:
+    """(sum_x sqrt(p(x) q(x)))^2 (the noise study's F_cl)."""
+    return float(np.sum(np.sqrt(np.clip(p, 0, None) * np.clip(q, 0, None))) ** 2)
+
+
+def tvd(p: np.ndarray, q: np.ndarray) -> float:
+    """Total variation distance (1/2) sum_x |p(x) - q(x)|."""
+    return float(0.5 * np.sum(np.abs(p - q)))
+

@@ -14,6 +14,9 @@ Conventions
   bit j <-> ``qubits[j]``.  CNOT(c, t) is ``Op("CNOT", (c, t))``, CZ is symmetric.
 * Parametric rotations carry ``param`` = index into a parameter vector; their
   ``params`` tuple holds the bound angle.
+* Noise channels (density-matrix runs) are ops too: ``Op("DEPOLARIZE", qubits, (p,))``
+  (1 or 2 qubits: every non-identity Pauli string with probability p / (4^k - 1)) and
+  ``Op("AMPDAMP", (q,), (gamma,))``.
 """
 from __future__ import annotations
 
@@ -26,8 +29,10 @@ import numpy as np
 __all__ = [
     "Op", "haar_u2", "brickwork", "brickwork_arrays", "ghz", "hea", "hea_params", "qft", "random_1q",
     "tfim_terms", "zz_chain_terms", "x_sum_terms", "bind", "inverse_ops",
-    "serving_stream", "Request",
+    "serving_stream", "Request", "with_depolarizing", "CHANNELS",
 ]
+
+CHANNELS = ("DEPOLARIZE", "AMPDAMP")
 
 
 @dataclasses.dataclass(frozen=True)
@@ -186,6 +191,20 @@ def inverse_ops(ops: Sequence[Op]) -> List[Op]:
 
 # ---------------------------------------------------------------- observables
 # A Pauli term is (coeff, ((qubit, 'X'|'Y'|'Z'), ...)).
+
+def with_depolarizing(ops: Sequence[Op], p1: float, p2: float) -> List[Op]:
+    """The circuit with a depolarizing channel after every gate: probability p1 on the
+    target of each 1-qubit gate, p2 on the pair of each 2-qubit gate (the noise model of
+    the Bell / GHZ noise study)."""
+    out: List[Op] = []
+    for op in ops:
+        out.append(op)
+        if len(op.qubits) == 1 and p1 > 0:
+            out.append(Op("DEPOLARIZE", op.qubits, (p1,)))
+        elif len(op.qubits) == 2 and p2 > 0:
+            out.append(Op("DEPOLARIZE", op.qubits, (p2,)))
+    return out
+
 
 def zz_chain_terms(n: int, periodic: bool = False, coeff: float = 1.0):
     terms = [(coeff, ((i, "Z"), (i + 1, "Z"))) for i in range(n - 1)]

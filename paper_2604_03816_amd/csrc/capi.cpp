@@ -1094,6 +1094,206 @@ qsv_status qsv_sample(qsv_state s, const int* qubits, int m, const double* unifo
     return QSV_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Superoperator of a channel with Kraus operators K (d x d each) on targets T, as a
+// (d^2 x d^2) matrix on (T, T + n): local row index r_row + d r_col, column c_row + d c_col,
+// entry sum_a K_a[r_row][c_row] conj(K_a[r_col][c_col]).
+std::vector<cd> superop(const std::vector<std::vector<cd>>& kraus, int d)
+{
+    const int D = d * d;
+    std::vector<cd> S((size_t)D * D, cd(0, 0));
+    for (const auto& K : kraus)
+        for (int rr = 0; rr < d; ++rr)
+            for (int rc = 0; rc < d; ++rc)
+                for (int cr = 0; cr < d; ++cr)
+                    for (int cc = 0; cc < d; ++cc)
+                        S[(size_t)(rr + d * rc) * D + (cr + d * cc)] +=
+                            K[(size_t)rr * d + cr] * std::conj(K[(size_t)rc * d + cc]);
+    return S;
+}
+
+bool dm_ops_to_gates(const qsv_dm_op* ops, size_t n_ops, int nsys, std::vector<InGate>& out, std::string& err)
+{
+    const cd I(0, 1);
+    const std::vector<std::vector<cd>> pauli = {{1, 0, 0, 1}, {0, 1, 1, 0}, {0, -I, I, 0}, {1, 0, 0, -1}};
+    for (size_t i = 0; i < n_ops; ++i) {
+        const qsv_dm_op& o = ops[i];
+        const std::string at = "op " + std::to_string(i) + ": ";
+        if (o.kind == 0) {
+            qsv_gate g{};
+            g.k = o.k;
+            for (int j = 0; j < 5; ++j) g.targets[j] = o.targets[j];
+            g.mat = o.mat;
+            InGate u;
+            if (!read_gate(g, nsys, u, err)) { err = at + err; return false; }
+            InGate v = u;
+            for (int j = 0; j < u.k; ++j) v.t[j] = u.t[j] + nsys;
+            for (cd& x : v.m) x = std::conj(x);
+            out.push_back(std::move(u));
+            out.push_back(std::move(v));
+            continue;
+        }
+        if (o.kind != 1 && o.kind != 2) { err = at + "kind must be 0, 1 or 2"; return false; }
+        if (!(o.p >= 0.0 && o.p <= 1.0)) { err = at + "channel probability must be in [0, 1]"; return false; }
+        const int k = o.k;
+        if (k < 1 || k > 2 || (o.kind == 2 && k != 1)) { err = at + "channel on 1 (or, depolarizing, 2) targets"; return false; }
+        for (int j = 0; j < k; ++j) {
+            if (o.targets[j] < 0 || o.targets[j] >= nsys) { err = at + "target out of range"; return false; }
+            for (int l = 0; l < j; ++l)
+                if (o.targets[l] == o.targets[j]) { err = at + "duplicate target"; return false; }
+        }
+        const int d = 1 << k;
+        std::vector<std::vector<cd>> kraus;
+        if (o.kind == 1) {
+            const int np = d * d - 1;   // non-identity Pauli strings
+            for (int a = 0; a <= np; ++a) {
+                const double w = std::sqrt(a == 0 ? 1.0 - o.p : o.p / np);
+                std::vector<cd> K((size_t)d * d);
+                for (int r = 0; r < d; ++r)
+                    for (int c = 0; c < d; ++c) {
+                        cd v = w;
+                        for (int j = 0; j < k; ++j) {   // Pauli (a >> 2j) & 3 on local bit j
+                            const int pj = (a >> (2 * j)) & 3;
+                            v *= pauli[pj][(size_t)((r >> j) & 1) * 2 + ((c >> j) & 1)];
+                        }
+                        K[(size_t)r * d + c] = v;
+                    }
+                kraus.push_back(std::move(K));
+            }
+        } else {
+            kraus.push_back({1, 0, 0, std::sqrt(1.0 - o.p)});
+            kraus.push_back({0, std::sqrt(o.p), 0, 0});
+        }
+        InGate g;
+        g.k = 2 * k;
+        for (int j = 0; j < kMaxK; ++j) g.t[j] = 0;
+        for (int j = 0; j < k; ++j) {
+            g.t[j] = o.targets[j];
+            g.t[k + j] = o.targets[j] + nsys;
+        }
+        g.m = superop(kraus, d);
+        out.push_back(std::move(g));
+    }
+    return true;
+}
+
+qsv_status dm_check(qsv_state s, int& nsys)
+{
+    qsv_status st = check_state(s);
+    if (st != QSV_OK) return st;
+    if (s->n < 2 || (s->n & 1)) return fail(QSV_E_ARG, "a density matrix needs a state of 2n qubits");
+    nsys = s->n / 2;
+    return QSV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+qsv_status qsv_dm_apply(qsv_state s, const qsv_dm_op* ops, size_t n_ops, const qsv_plan_opts* opts)
+{
+    int nsys = 0;
+    qsv_status st = dm_check(s, nsys);
+    if (st != QSV_OK) return st;
+    if (n_ops && !ops) return fail(QSV_E_ARG, "ops is null");
+    std::vector<InGate> gates;
+    std::string err;
+    if (!dm_ops_to_gates(ops, n_ops, nsys, gates, err)) return fail(QSV_E_ARG, err);
+    if (gates.empty()) return QSV_OK;
+    PlanOpts o;
+    if (!plan_opts_from(s->dtype, opts, o, err)) return fail(QSV_E_ARG, err);
+    HostPlan hp;
+    if (!make_plan(s->n, s->dtype, gates, o, hp, err)) return fail(QSV_E_ARG, err);
+    DeviceGuard g(s->device);
+    if ((st = enqueue_plan(s, hp)) != QSV_OK) return st;
+    QSV_HIP(hipStreamSynchronize(s->stream));
+    return QSV_OK;
+}
+
+qsv_status qsv_dm_probs(qsv_state s, const int* qubits, int m, double* out)
+{
+    int nsys = 0;
+    qsv_status st = dm_check(s, nsys);
+    if (st != QSV_OK) return st;
+    if (!out) return fail(QSV_E_ARG, "out is null");
+    if (!qubits) m = nsys;
+    if (m < 1 || m > nsys) return fail(QSV_E_ARG, "m must be in [1, n]");
+    MargArgs a{};
+    a.n = nsys;
+    a.m = m;
+    unsigned long long Q = 0;
+    for (int j = 0; j < m; ++j) {
+        const int q = qubits ? qubits[j] : j;
+        if (q < 0 || q >= nsys) return fail(QSV_E_ARG, "qubit out of range");
+        if ((Q >> q) & 1) return fail(QSV_E_ARG, "repeated qubit");
+        a.q[j] = q;
+        Q |= 1ull << q;
+    }
+    int r = 0;
+    for (int b = 0; b < nsys; ++b)
+        if (!((Q >> b) & 1)) a.rest[r++] = b;
+    const long long M = 1ll << m, Rn = 1ll << (nsys - m);
+    long long nchunks = std::min(std::max<long long>(1, (1ll << 16) / M), Rn);
+    a.nchunks = nchunks;
+    a.chunk = Rn / nchunks;
+    const size_t pbytes = (size_t)(M * nchunks) * 2 * sizeof(double);
+    const size_t obytes = (size_t)M * sizeof(double);
+    DeviceGuard g(s->device);
+    if ((st = ensure_work(s, pbytes + obytes)) != QSV_OK) return st;
+    double* partial = s->d_work;
+    double* dout = (double*)((char*)s->d_work + pbytes);
+    QSV_HIP(launch_probs_marg(s->dtype, s->buf, a, partial, dout, s->stream, true));
+    QSV_HIP(hipMemcpyAsync(out, dout, obytes, hipMemcpyDeviceToHost, s->stream));
+    QSV_HIP(hipStreamSynchronize(s->stream));
+    return QSV_OK;
+}
+
+qsv_status qsv_dm_expval_pauli(qsv_state s, const qsv_pauli_term* terms, size_t n_terms, double* per_term,
+                               double* sum)
+{
+    int nsys = 0;
+    qsv_status st = dm_check(s, nsys);
+    if (st != QSV_OK) return st;
+    if (n_terms && !terms) return fail(QSV_E_ARG, "terms is null");
+    std::vector<PTerm> pt;
+    std::string err;
+    if (!parse_terms(terms, n_terms, nsys, pt, err)) return fail(QSV_E_ARG, err);
+    DeviceGuard g(s->device);
+    const int grid = (int)std::min<long long>(1024, std::max<long long>(1, (1ll << nsys) / kThreads));
+    NS total;
+    for (size_t b0 = 0; b0 < pt.size(); b0 += kMaxPauliApply) {
+        PauliSumArgs p{};
+        p.nterms = (int)std::min<size_t>(kMaxPauliApply, pt.size() - b0);
+        for (int i = 0; i < p.nterms; ++i) {
+            p.x[i] = (long long)pt[b0 + i].x;
+            p.z[i] = (long long)pt[b0 + i].z;
+            p.ny[i] = pt[b0 + i].ny;
+            p.coeff[i] = pt[b0 + i].coeff;
+        }
+        const size_t bytes = (size_t)grid * p.nterms * 2 * sizeof(double);
+        if ((st = ensure_work(s, bytes)) != QSV_OK) return st;
+        if ((st = ensure_hwork(s, bytes)) != QSV_OK) return st;
+        QSV_HIP(launch_dm_pauli(s->dtype, s->buf, nsys, p, grid, s->d_work, s->stream));
+        QSV_HIP(hipMemcpyAsync(s->h_work, s->d_work, bytes, hipMemcpyDeviceToHost, s->stream));
+        QSV_HIP(hipStreamSynchronize(s->stream));
+        for (int i = 0; i < p.nterms; ++i) {
+            NS acc;
+            for (int b = 0; b < grid; ++b) {
+                acc.add(s->h_work[((size_t)b * p.nterms + i) * 2]);
+                acc.c += s->h_work[((size_t)b * p.nterms + i) * 2 + 1];
+            }
+            const double v = pt[b0 + i].coeff * acc.value();
+            if (per_term) per_term[b0 + i] = v;
+            total.add(v);
+        }
+    }
+    if (sum) *sum = total.value();
+    return QSV_OK;
+}
+
 qsv_status qsv_adjoint_grad(int n, qsv_dtype dtype, const qsv_op* ops, size_t n_ops, const double* params, int B,
                             int P, const qsv_pauli_term* H, size_t n_terms, double* energy, double* grad,
                             void* stream)

@@ -889,7 +889,9 @@ __global__ __launch_bounds__(kThreads) void k_probs_full(const C* __restrict__ s
     }
 }
 
-template <typename C>
+// DM: the buffer holds vec(rho) of an a.n-qubit density matrix (index row + 2^n col)
+// and the probability of basis state k is the diagonal entry Re rho[k, k].
+template <typename C, bool DM>
 __global__ __launch_bounds__(kThreads) void k_probs_marg(const C* __restrict__ st, const MargArgs a,
                                                          double* __restrict__ partial)
 {
@@ -906,9 +908,13 @@ __global__ __launch_bounds__(kThreads) void k_probs_marg(const C* __restrict__ s
     for (long long r = ch * a.chunk; r < (ch + 1) * a.chunk; ++r) {
         long long idx = ob;
         for (int j = 0; j < nr; ++j) idx |= ((r >> j) & 1) << a.rest[j];
-        const C v = st[idx];
-        const double x = v.x, y = v.y;
-        nadd(s, x * x + y * y);
+        if (DM) {
+            nadd(s, (double)st[idx + (idx << a.n)].x);
+        } else {
+            const C v = st[idx];
+            const double x = v.x, y = v.y;
+            nadd(s, x * x + y * y);
+        }
     }
     partial[2 * (ch * M + o)] = s.s;
     partial[2 * (ch * M + o) + 1] = s.c;
@@ -973,6 +979,35 @@ __global__ __launch_bounds__(kThreads) void k_zsum_batch(const ZItem* __restrict
         for (int b = 0; b < kZChunkQubits; ++b) {
             r = block_reduce(NSum{bits[b], 0.0}, scratch);
             if (threadIdx.x == 0) out[1 + b] = r.s + r.c;
+        }
+    }
+}
+
+// Tr(rho P_t) for an n-qubit density matrix held as vec(rho) (index row + 2^n col):
+// P|k> = i^ny (-1)^popcount(k & z) |k xor x>, so Tr(rho P) = sum_k rho[k, k xor x] *
+// i^ny (-1)^popcount(k & z).  Only 2^n entries per term are read.  One FP64 Neumaier
+// pair per workgroup and term, combined on the host in a fixed order.
+template <typename C>
+__global__ __launch_bounds__(kThreads) void k_dm_pauli(const C* __restrict__ st, int n, const PauliSumArgs p,
+                                                       double* __restrict__ partial)
+{
+    __shared__ NSum scratch[kThreads / 64];
+    const long long N = 1ll << n;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (int t = 0; t < p.nterms; ++t) {
+        const long long x = p.x[t], z = p.z[t];
+        const int q = p.ny[t] & 3;
+        NSum acc = {0.0, 0.0};
+        for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < N; k += stride) {
+            const C v = st[k + ((k ^ x) << n)];
+            double val = (q == 0) ? v.x : (q == 1) ? -v.y : (q == 2) ? -v.x : v.y;   // Re(i^q v)
+            if (__popcll(k & z) & 1) val = -val;
+            nadd(acc, val);
+        }
+        const NSum r = block_reduce(acc, scratch);
+        if (threadIdx.x == 0) {
+            partial[((long long)blockIdx.x * p.nterms + t) * 2] = r.s;
+            partial[((long long)blockIdx.x * p.nterms + t) * 2 + 1] = r.c;
         }
     }
 }
@@ -1141,17 +1176,18 @@ hipError_t launch_probs_full(int dtype, const void* st, long long N, void* out, 
 }
 
 hipError_t launch_probs_marg(int dtype, const void* st, const MargArgs& a, double* partial, double* out,
-                             hipStream_t s)
+                             hipStream_t s, bool density)
 {
     const long long M = 1ll << a.m;
     const long long total = M * a.nchunks;
     const long long blocks = (total + kThreads - 1) / kThreads;
-    if (dtype == 0)
-        hipLaunchKernelGGL(k_probs_marg<float2>, dim3((unsigned)blocks), dim3(kThreads), 0, s,
-                           (const float2*)st, a, partial);
-    else
-        hipLaunchKernelGGL(k_probs_marg<double2>, dim3((unsigned)blocks), dim3(kThreads), 0, s,
-                           (const double2*)st, a, partial);
+    if (dtype == 0) {
+        auto k = density ? k_probs_marg<float2, true> : k_probs_marg<float2, false>;
+        hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kThreads), 0, s, (const float2*)st, a, partial);
+    } else {
+        auto k = density ? k_probs_marg<double2, true> : k_probs_marg<double2, false>;
+        hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kThreads), 0, s, (const double2*)st, a, partial);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sum_chunks, dim3((unsigned)((M + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
@@ -1177,6 +1213,16 @@ hipError_t launch_sample_chunks(int src_dtype, const void* src, int chunk_bits, 
     const size_t lds = sizeof(double) << chunk_bits;
     auto k = src_dtype == 0 ? k_sample_chunks<0> : src_dtype == 1 ? k_sample_chunks<1> : k_sample_chunks<2>;
     hipLaunchKernelGGL(k, dim3((unsigned)nlist), dim3(kThreads), lds, s, src, chunk_bits, list, residual, outcome);
+    return hipGetLastError();
+}
+
+hipError_t launch_dm_pauli(int dtype, const void* st, int n, const PauliSumArgs& p, int grid, double* partial,
+                           hipStream_t s)
+{
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_dm_pauli<float2>, dim3(grid), dim3(kThreads), 0, s, (const float2*)st, n, p, partial);
+    else
+        hipLaunchKernelGGL(k_dm_pauli<double2>, dim3(grid), dim3(kThreads), 0, s, (const double2*)st, n, p, partial);
     return hipGetLastError();
 }
 

@@ -146,6 +146,8 @@ hipError_t launch_chunk_totals(int src_dtype, const void* src, int chunk_bits, l
 hipError_t launch_sample_chunks(int src_dtype, const void* src, int chunk_bits, const SampleChunk* list,
                                 long long nlist, const double* residual, long long* outcome, hipStream_t s);
 hipError_t launch_probs_marg(int dtype, const void* st, const MargArgs& a, double* partial, double* out,
-                             hipStream_t s);
+                             hipStream_t s, bool density = false);
+hipError_t launch_dm_pauli(int dtype, const void* st, int n, const PauliSumArgs& p, int grid, double* partial,
+                           hipStream_t s);
 
 }  // namespace qsv

@@ -50,6 +50,11 @@ class PlanStats(ctypes.Structure):
         return {f[0]: getattr(self, f[0]) for f in self._fields_}
 
 
+class DMOp(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("k", ctypes.c_int), ("targets", ctypes.c_int * 5),
+                ("mat", ctypes.POINTER(ctypes.c_double)), ("p", ctypes.c_double)]
+
+
 class PauliTerm(ctypes.Structure):
     _fields_ = [("coeff", ctypes.c_double), ("n", ctypes.c_int), ("qubits", ctypes.POINTER(ctypes.c_int)),
                 ("paulis", ctypes.c_char_p)]
@@ -65,6 +70,7 @@ EXPORTS = [
     "qsv_set_state", "qsv_gate_matrix", "qsv_plan_create", "qsv_plan_free", "qsv_plan_get_stats",
     "qsv_plan_fused_gate", "qsv_plan_pass_info", "qsv_plan_pass_ops", "qsv_plan_emulate", "qsv_plan_apply", "qsv_plan_apply_range",
     "qsv_apply_fused", "qsv_sync", "qsv_norm", "qsv_expval_pauli", "qsv_probs", "qsv_sample", "qsv_adjoint_grad",
+    "qsv_dm_apply", "qsv_dm_probs", "qsv_dm_expval_pauli",
     "qsv_server_create", "qsv_server_free", "qsv_server_submit", "qsv_server_step", "qsv_server_results",
     "qsv_server_get_stats", "qsv_server_get_state", "qsv_server_release",
 ]
@@ -104,6 +110,10 @@ def lib():
     L.qsv_norm.argtypes = [vp, dp]
     L.qsv_expval_pauli.argtypes = [vp, ctypes.POINTER(PauliTerm), sz, dp, dp]
     L.qsv_probs.argtypes = [vp, ctypes.POINTER(i), i, vp, i]
+    L.qsv_dm_apply.argtypes = [vp, ctypes.POINTER(DMOp), sz, ctypes.POINTER(PlanOpts)]
+    L.qsv_dm_probs.argtypes = [vp, ctypes.POINTER(i), i, ctypes.POINTER(ctypes.c_double)]
+    L.qsv_dm_expval_pauli.argtypes = [vp, ctypes.POINTER(PauliTerm), sz, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_double)]
     L.qsv_sample.argtypes = [vp, ctypes.POINTER(i), i, ctypes.POINTER(ctypes.c_double), ctypes.c_longlong,
                              ctypes.POINTER(ctypes.c_longlong)]
     L.qsv_adjoint_grad.argtypes = [i, i, ctypes.POINTER(COp), sz, dp, i, i, ctypes.POINTER(PauliTerm), sz,
@@ -485,3 +495,78 @@ def adjoint_grad(n: int, template, params, terms, dtype: str = "c128", stream=No
     check(lib().qsv_adjoint_grad(n, _DT[dtype], ol.arr, ol.n, _dptr(p), B, P, tl.arr, tl.n, _dptr(E), _dptr(G),
                                  ctypes.c_void_p(s.cuda_stream)))
     return (E[0], G[0]) if single else (E, G)
+
+
+# ------------------------------------------------------------------ density matrices
+
+_CHANNEL_KIND = {"DEPOLARIZE": 1, "AMPDAMP": 2}
+
+
+class DMOpList:
+    """Gates and noise channels marshalled into qsv_dm_op structs."""
+
+    def __init__(self, ops: Iterable):
+        ops = list(ops)
+        self.n = len(ops)
+        self.arr = (DMOp * max(1, len(ops)))()
+        self._keep = []
+        for i, op in enumerate(ops):
+            d = self.arr[i]
+            k = len(op.qubits)
+            d.k = k
+            d.targets[:k] = op.qubits
+            kind = _CHANNEL_KIND.get(op.name, 0)
+            d.kind = kind
+            if kind:
+                d.p = float(op.params[0])
+                continue
+            m = op.matrix if op.name == "U" else _named(op.name, op.params)
+            buf = np.ascontiguousarray(m, dtype=np.complex128).reshape(-1)
+            self._keep.append(buf)
+            d.mat = buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class DensityMatrix:
+    """An n-qubit density matrix held as vec(rho) in a 2n-qubit State (starts as
+    |0...0><0...0|); gates act as U rho U^dagger, channels through their Kraus
+    operators, all applied by libqsv's planner and kernels."""
+
+    def __init__(self, n: int, dtype: str = "c128", device: str = "cuda:0", stream=None):
+        self.n = n
+        self.dtype = dtype
+        self.state = State(2 * n, dtype, device=device, stream=stream)
+
+    def apply(self, ops, **opts) -> None:
+        ol = ops if isinstance(ops, DMOpList) else DMOpList(ops)
+        po = _opts(**opts) if opts else None
+        check(lib().qsv_dm_apply(self.state.h, ol.arr, ol.n, ctypes.byref(po) if po is not None else None))
+
+    def reset(self) -> None:
+        self.state.reset()
+
+    def probs(self, qubits: Optional[Sequence[int]] = None) -> np.ndarray:
+        m = self.n if qubits is None else len(qubits)
+        qp = None
+        if qubits is not None:
+            qa = (ctypes.c_int * m)(*[int(q) for q in qubits])
+            qp = ctypes.cast(qa, ctypes.POINTER(ctypes.c_int))
+        out = np.empty(1 << m, dtype=np.float64)
+        check(lib().qsv_dm_probs(self.state.h, qp, m, _dptr(out)))
+        return out
+
+    def expval(self, terms, per_term: bool = False):
+        tl = terms if isinstance(terms, TermList) else TermList(terms)
+        per = np.zeros(max(1, tl.n), dtype=np.float64)
+        tot = ctypes.c_double()
+        check(lib().qsv_dm_expval_pauli(self.state.h, tl.arr, tl.n, _dptr(per), ctypes.byref(tot)))
+        return (tot.value, per[: tl.n].copy()) if per_term else tot.value
+
+    def matrix(self) -> np.ndarray:
+        """rho as a dense 2^n x 2^n host array (small n)."""
+        v = self.state.get()
+        N = 1 << self.n
+        return v.reshape(N, N).T.copy()   # vec index row + N col
+
+    def free(self) -> None:
+        self.state.free()
+

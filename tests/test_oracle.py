@@ -393,3 +393,72 @@ def test_sampling_frequencies_and_bit_order():
     freq = np.bincount(got, minlength=4) / shots
     sigma = np.sqrt(expect * (1 - expect) / shots)
     assert np.all(np.abs(freq - expect) < 5 * sigma)
+
+
+# ------------------------------------------------------------------ density matrices (Table 8)
+
+def _ghz_depolarized(n, p):
+    ops = [C.Op("H", (0,)), C.Op("DEPOLARIZE", (0,), (p,))]
+    for t in range(1, n):
+        ops += [C.Op("CNOT", (0, t)), C.Op("DEPOLARIZE", (0,), (p,)), C.Op("DEPOLARIZE", (t,), (p,))]
+    return ops
+
+
+def test_noise_study_matches_table8():
+    """The exact (infinite-shot) F_cl and TVD of the noise study agree with the paper's
+    MSLE column within its 8192-shot noise; a depolarizing convention of p/4 per Pauli
+    instead of p/3 would be off by about 0.009 on average."""
+    table = golden("noise_study_msle")
+    devs = []
+    for n in (2, 3, 4, 5):
+        rho = oracle.dm_simulate(n, _ghz_depolarized(n, 0.01))
+        pn = oracle.dm_probs(rho, list(range(n)))
+        pi = np.zeros(1 << n)
+        pi[0] = pi[-1] = 0.5
+        F, T = oracle.classical_fidelity(pi, pn), oracle.tvd(pi, pn)
+        want_F, want_T = table[str(n)]
+        assert abs(F - want_F) < 0.006 and abs(T - want_T) < 0.006
+        devs.append(abs(F - want_F))
+    assert np.mean(devs) < 0.004
+
+
+def test_depolarized_bell_closed_form():
+    # H(0) depol(0), CNOT depol(0) depol(1): a bit flip (X or Y) with probability 2p/3 per
+    # qubit on the final Bell pair; Z errors before the CNOT do not change Z outcomes
+    for p in (0.0, 0.01, 0.2, 0.75):
+        rho = oracle.dm_simulate(2, _ghz_depolarized(2, p))
+        q = 2 * p / 3
+        anti = 2 * q * (1 - q)
+        probs = oracle.dm_probs(rho, [0, 1])
+        assert np.allclose(probs, [(1 - anti) / 2, anti / 2, anti / 2, (1 - anti) / 2], atol=1e-14)
+        # each depolarizing channel scales Bloch components by 1 - 4p/3
+        zz = oracle.dm_expval(rho, [(1.0, ((0, "Z"), (1, "Z")))])
+        assert abs(zz - (1 - 4 * p / 3) ** 2) < 1e-14
+
+
+def test_density_matrix_invariants_and_special_cases():
+    rng = np.random.default_rng(21)
+    n = 3
+    ops = C.random_1q(n, 5, gates_per_qubit=2) + [C.Op("CNOT", (0, 2)), C.Op("CZ", (1, 2))]
+    # no noise: the pure state's projector
+    psi = oracle.simulate(n, ops)
+    assert np.allclose(oracle.dm_simulate(n, ops), np.outer(psi, psi.conj()), atol=1e-14)
+    # random noise: unit trace, Hermitian, positive semidefinite
+    noisy = []
+    for op in ops:
+        noisy.append(op)
+        noisy.append(C.Op("DEPOLARIZE", op.qubits, (float(rng.uniform(0, 0.3)),)))
+        noisy.append(C.Op("AMPDAMP", (op.qubits[0],), (float(rng.uniform(0, 0.3)),)))
+    rho = oracle.dm_simulate(n, noisy)
+    assert abs(np.trace(rho) - 1) < 1e-13
+    assert np.allclose(rho, rho.conj().T, atol=1e-14)
+    assert np.min(np.linalg.eigvalsh(rho)) > -1e-13
+    # fully depolarizing channels give the maximally mixed state
+    one = oracle.dm_simulate(1, [C.Op("H", (0,)), C.Op("DEPOLARIZE", (0,), (0.75,))])
+    assert np.allclose(one, np.eye(2) / 2, atol=1e-15)
+    two = oracle.dm_simulate(2, [C.Op("H", (0,)), C.Op("CNOT", (0, 1)), C.Op("DEPOLARIZE", (0, 1), (15 / 16,))])
+    assert np.allclose(two, np.eye(4) / 4, atol=1e-15)
+    # amplitude damping of |1>: population gamma moves to |0>
+    g = 0.3
+    ad = oracle.dm_simulate(1, [C.Op("X", (0,)), C.Op("AMPDAMP", (0,), (g,))])
+    assert np.allclose(ad, np.diag([g, 1 - g]), atol=1e-15)
