@@ -32,6 +32,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-c128
        [--no-serve] [--no-precision] [--no-adjoint] [--no-sampling] [--no-noise] [--copy-probe]
 """
 import argparse
+import dataclasses
 import json
 import math
 import os
@@ -241,12 +242,20 @@ def serving(args):
     batched = serve.run_batched(reqs, circuits, sv)
     sv.close()
     torch.cuda.empty_cache()
+    # the same stream with the precision left to the server (Eq. 12, default tolerance;
+    # complex64 runs whose norm drifts by more than 1e-5 are repeated in complex128)
+    auto_reqs = [dataclasses.replace(r, dtype="auto") for r in reqs]
+    sv = serve.Server(max_slots=64, use_graph=True, norm_guard=1e-5)
+    auto = serve.run_batched(auto_reqs, circuits, sv)
+    sv.close()
+    torch.cuda.empty_cache()
     k = min(args.plain_requests, len(reqs))
     plain = serve.run_plain(reqs[:k], circuits[:k], fuse=False)
     return {"workload": "%d requests, n~U{12..26}, brickwork depth~U{10..60}, 70%% complex64, Poisson 200/s, "
                         "seed 5" % len(reqs),
             "offered_per_s": 200.0, "input_generation_s": gen_s,
             "batched": batched,
+            "batched_auto_precision": auto,
             "plain": dict(plain, note="first %d requests of the same stream, one at a time, unfused" % k)}
 
 

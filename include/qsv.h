@@ -42,7 +42,7 @@ typedef enum {
     QSV_E_UNSUPPORTED = 4   /* valid request outside what this build supports */
 } qsv_status;
 
-typedef enum { QSV_C64 = 0, QSV_C128 = 1 } qsv_dtype;
+typedef enum { QSV_C64 = 0, QSV_C128 = 1, QSV_AUTO = 2 } qsv_dtype;   /* AUTO: serving only */
 
 typedef struct qsv_state_s* qsv_state;   /* opaque */
 typedef struct qsv_plan_s* qsv_plan;     /* opaque */
@@ -303,6 +303,10 @@ typedef struct {
     int planner_threads;    /* host planning threads; 0 = 4 */
     int keep_states;        /* 1: finished states stay on the device until qsv_server_release */
     int dry_run;            /* 1: no device work at all (admission and scheduling only) */
+    double eps_tol;         /* QSV_AUTO requests: complex64 when Eq. 12 holds for this
+                               tolerance (qsv_precision_select); 0 = its default */
+    double norm_guard;      /* QSV_AUTO requests run in complex64 are run again in
+                               complex128 when |norm - 1| exceeds this; 0 = no guard */
 } qsv_server_opts;
 
 typedef struct {
@@ -312,11 +316,14 @@ typedef struct {
     double zexp[34];        /* <Z_i>, i < n */
     double t_submit, t_admit, t_finish;   /* seconds on the server's clock */
     long long passes, fused;
+    int requested;          /* the dtype asked for (QSV_AUTO possible); dtype is the one used */
+    int promoted;           /* 1: first run in complex64, repeated in complex128 by the guard */
 } qsv_result;
 
 typedef struct {
     long long submitted, admitted, finished, rejected, steps, graph_replays, tiles, admission_waits;
     long long peak_running, peak_used_bytes, capacity_bytes, used_bytes, running, pending;
+    long long auto_c64, auto_c128, promoted;   /* QSV_AUTO requests: precision chosen, rerun */
 } qsv_server_stats;
 
 /* stream: hipStream_t for all of the server's device work (NULL: the server creates
@@ -325,8 +332,16 @@ typedef struct {
 qsv_status qsv_server_create(const qsv_server_opts* opts, void* stream, qsv_server* out);
 qsv_status qsv_server_free(qsv_server s);
 
-/* Queues a request (gates copied; planning starts on a host thread).  popts may be
- * NULL (defaults).  *id receives the request id.  Errors: QSV_E_ARG. */
+/* Adaptive precision (Section 5.4): the rounding bound of Eq. 11 for complex64,
+ * g * 2^n * 1.19e-7 (g gate applications on 2^n amplitudes), against eps_tol (Eq. 12):
+ * complex64 when it holds, else complex128.  eps_tol <= 0 selects the default
+ * 49.5 * 2^20 * 1.19e-7 (about 6.18): the paper's 20-qubit circuits of fewer than 50 gates
+ * then run in complex64 and deeper ones in complex128 (Section 8.4). */
+qsv_status qsv_precision_select(int n_qubits, size_t n_gates, double eps_tol, qsv_dtype* out);
+
+/* Queues a request (gates copied; planning starts on a host thread).  dtype QSV_AUTO
+ * selects the precision by qsv_precision_select with the server's eps_tol.  popts may
+ * be NULL (defaults).  *id receives the request id.  Errors: QSV_E_ARG. */
 qsv_status qsv_server_submit(qsv_server s, int n_qubits, qsv_dtype dtype, const qsv_gate* gates,
                              size_t n_gates, const qsv_plan_opts* popts, long long* id);
 

@@ -48,6 +48,9 @@ struct Req {
     long long id = 0;
     int n = 0;
     int dtype = 0;
+    int requested = 0;   // the dtype asked for (QSV_AUTO possible)
+    int promoted = 0;
+    bool keep_gates = false;   // an automatic complex64 run that the norm guard may repeat
     PlanOpts popts;
     std::vector<InGate> gates;
     HostPlan plan;
@@ -141,8 +144,10 @@ void worker_loop(qsv_server s)
             const long long chunks = 1ll << std::max(0, r->n - kZQ);
             r->work_bytes = (size_t)chunks * (kZQ + 1) * sizeof(double);
             r->footprint = r->state_bytes + r->table_bytes + r->work_bytes;   // Eq. 14
-            r->gates.clear();
-            r->gates.shrink_to_fit();
+            if (!r->keep_gates) {
+                r->gates.clear();
+                r->gates.shrink_to_fit();
+            }
             r->planned.store(1);
         } else {
             r->err = err;
@@ -448,10 +453,18 @@ qsv_status qsv_server_submit(qsv_server s, int n, qsv_dtype dtype, const qsv_gat
 {
     if (!s || !id) return set_error(QSV_E_ARG, "null argument");
     if (n < 1 || n > kMaxQubits) return set_error(QSV_E_ARG, "n_qubits must be in [1, 34]");
-    if (dtype != QSV_C64 && dtype != QSV_C128) return set_error(QSV_E_ARG, "bad dtype");
+    if (dtype != QSV_C64 && dtype != QSV_C128 && dtype != QSV_AUTO) return set_error(QSV_E_ARG, "bad dtype");
     if (n_gates && !gates) return set_error(QSV_E_ARG, "gates is null");
     auto r = std::make_shared<Req>();
     r->n = n;
+    r->requested = dtype;
+    if (dtype == QSV_AUTO) {
+        qsv_dtype chosen = QSV_C128;
+        (void)qsv_precision_select(n, n_gates, s->o.eps_tol, &chosen);
+        dtype = chosen;
+        r->keep_gates = (dtype == QSV_C64 && s->o.norm_guard > 0);
+        ++(dtype == QSV_C64 ? s->st.auto_c64 : s->st.auto_c128);
+    }
     r->dtype = dtype;
     std::string oerr;
     if (!plan_opts_from(dtype, popts, r->popts, oerr)) return set_error(QSV_E_ARG, oerr);
@@ -626,6 +639,38 @@ qsv_status qsv_server_step(qsv_server s, int* n_running, int* n_pending)
             res.norm = tot + tc;
             for (int b = 0; b < r->n; ++b) res.zexp[b] = res.norm - 2.0 * (ones[b] + oc[b]);
         }
+        res.requested = r->requested;
+        res.promoted = r->promoted;
+        if (r->keep_gates && !s->o.dry_run && std::fabs(res.norm - 1.0) > s->o.norm_guard) {
+            // the complex64 run drifted: run the request again in complex128, ahead of
+            // the queue, under the same id and arrival time
+            auto q = std::make_shared<Req>();
+            q->id = r->id;
+            q->n = r->n;
+            q->dtype = QSV_C128;
+            q->requested = r->requested;
+            q->promoted = 1;
+            q->t_submit = r->t_submit;
+            std::string oerr;
+            (void)plan_opts_from(QSV_C128, nullptr, q->popts, oerr);
+            const int cap = kServeTileQubits[QSV_C128];
+            q->popts.tile_qubits = std::min(q->popts.tile_qubits, cap);
+            q->popts.whole_state_max = std::min(q->popts.whole_state_max, cap);
+            q->popts.mfma_lds_floats = std::min(q->popts.mfma_lds_floats, kServeOperandFloats);
+            if (q->popts.low_qubits >= q->popts.tile_qubits) q->popts.low_qubits = q->popts.tile_qubits - 1;
+            q->popts.fuse = r->popts.fuse;
+            if (q->popts.fuse == 0) q->popts.max_ops_per_pass = 1;
+            q->gates.swap(r->gates);
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                s->plan_q.push_front(q);
+                s->pending.push_front(q);
+            }
+            s->cv.notify_one();
+            ++s->st.promoted;
+            release_req(s, *r);
+            continue;
+        }
         s->done.push_back(res);
         ++s->st.finished;
         if (s->o.keep_states && !s->o.dry_run) {
@@ -643,6 +688,21 @@ qsv_status qsv_server_step(qsv_server s, int* n_running, int* n_pending)
     for (auto& r : s->running) r->next_pass += P;
     if (n_running) *n_running = (int)s->running.size();
     if (n_pending) *n_pending = (int)s->pending.size();
+    return QSV_OK;
+}
+
+// Default tolerance of Eq. 12: 49.5 gates x 2^20 x 1.19e-7, so that at 20 qubits circuits
+// of fewer than 50 gates run in complex64 and those of 50 or more in complex128 (Section
+// 8.4); the Section 5.4 example (20 qubits, 200 gates: about 25) stays in complex128.
+constexpr double kDefaultEpsTol = 49.5 * 1048576.0 * 1.19e-7;
+
+qsv_status qsv_precision_select(int n, size_t n_gates, double eps_tol, qsv_dtype* out)
+{
+    if (!out) return set_error(QSV_E_ARG, "out is null");
+    if (n < 1 || n > kMaxQubits) return set_error(QSV_E_ARG, "n_qubits must be in [1, 34]");
+    const double tol = eps_tol > 0 ? eps_tol : kDefaultEpsTol;
+    const double bound = (double)n_gates * std::ldexp(1.0, n) * 1.19e-7;   // Eq. 11, complex64
+    *out = bound <= tol ? QSV_C64 : QSV_C128;                               // Eq. 12
     return QSV_OK;
 }
 

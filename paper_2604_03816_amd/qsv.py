@@ -18,8 +18,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "_build", "libqsv.so")
 
 QSV_OK, QSV_E_ARG, QSV_E_OOM, QSV_E_DEVICE, QSV_E_UNSUPPORTED = 0, 1, 2, 3, 4
-C64, C128 = 0, 1
+C64, C128, AUTO = 0, 1, 2
 _DT = {"c64": C64, "c128": C128, "complex64": C64, "complex128": C128}
+_DT_SERVE = dict(_DT, auto=AUTO)   # the server also takes "auto" (precision by Eq. 12)
 _STATUS = {1: "QSV_E_ARG", 2: "QSV_E_OOM", 3: "QSV_E_DEVICE", 4: "QSV_E_UNSUPPORTED"}
 
 
@@ -70,7 +71,7 @@ EXPORTS = [
     "qsv_set_state", "qsv_gate_matrix", "qsv_plan_create", "qsv_plan_free", "qsv_plan_get_stats",
     "qsv_plan_fused_gate", "qsv_plan_pass_info", "qsv_plan_pass_ops", "qsv_plan_emulate", "qsv_plan_apply", "qsv_plan_apply_range",
     "qsv_apply_fused", "qsv_sync", "qsv_norm", "qsv_expval_pauli", "qsv_probs", "qsv_sample", "qsv_adjoint_grad",
-    "qsv_dm_apply", "qsv_dm_probs", "qsv_dm_expval_pauli",
+    "qsv_dm_apply", "qsv_dm_probs", "qsv_dm_expval_pauli", "qsv_precision_select",
     "qsv_server_create", "qsv_server_free", "qsv_server_submit", "qsv_server_step", "qsv_server_results",
     "qsv_server_get_stats", "qsv_server_get_state", "qsv_server_release",
 ]
@@ -110,6 +111,7 @@ def lib():
     L.qsv_norm.argtypes = [vp, dp]
     L.qsv_expval_pauli.argtypes = [vp, ctypes.POINTER(PauliTerm), sz, dp, dp]
     L.qsv_probs.argtypes = [vp, ctypes.POINTER(i), i, vp, i]
+    L.qsv_precision_select.argtypes = [i, sz, ctypes.c_double, ctypes.POINTER(i)]
     L.qsv_dm_apply.argtypes = [vp, ctypes.POINTER(DMOp), sz, ctypes.POINTER(PlanOpts)]
     L.qsv_dm_probs.argtypes = [vp, ctypes.POINTER(i), i, ctypes.POINTER(ctypes.c_double)]
     L.qsv_dm_expval_pauli.argtypes = [vp, ctypes.POINTER(PauliTerm), sz, ctypes.POINTER(ctypes.c_double),
@@ -569,4 +571,11 @@ class DensityMatrix:
 
     def free(self) -> None:
         self.state.free()
+
+
+def precision_select(n: int, n_gates: int, eps_tol: float = 0.0) -> str:
+    """Eq. 12: "c64" when g * 2^n * 1.19e-7 <= eps_tol (default about 6.18), else "c128"."""
+    out = ctypes.c_int()
+    check(lib().qsv_precision_select(n, n_gates, eps_tol, ctypes.byref(out)))
+    return "c64" if out.value == C64 else "c128"
 

@@ -23,20 +23,21 @@ class ServerOpts(ctypes.Structure):
     _fields_ = [("capacity_bytes", ctypes.c_size_t), ("reserve_bytes", ctypes.c_size_t),
                 ("max_slots", ctypes.c_int), ("passes_per_step", ctypes.c_int), ("grid", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("planner_threads", ctypes.c_int), ("keep_states", ctypes.c_int),
-                ("dry_run", ctypes.c_int)]
+                ("dry_run", ctypes.c_int), ("eps_tol", ctypes.c_double), ("norm_guard", ctypes.c_double)]
 
 
 class Result(ctypes.Structure):
     _fields_ = [("id", ctypes.c_longlong), ("n", ctypes.c_int), ("dtype", ctypes.c_int), ("status", ctypes.c_int),
                 ("norm", ctypes.c_double), ("zexp", ctypes.c_double * 34), ("t_submit", ctypes.c_double),
                 ("t_admit", ctypes.c_double), ("t_finish", ctypes.c_double), ("passes", ctypes.c_longlong),
-                ("fused", ctypes.c_longlong)]
+                ("fused", ctypes.c_longlong), ("requested", ctypes.c_int), ("promoted", ctypes.c_int)]
 
 
 class ServerStats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_longlong) for f in (
         "submitted", "admitted", "finished", "rejected", "steps", "graph_replays", "tiles", "admission_waits",
-        "peak_running", "peak_used_bytes", "capacity_bytes", "used_bytes", "running", "pending")]
+        "peak_running", "peak_used_bytes", "capacity_bytes", "used_bytes", "running", "pending",
+        "auto_c64", "auto_c128", "promoted")]
 
 
 _BOUND = False
@@ -64,7 +65,8 @@ def _bind():
 class Server:
     def __init__(self, max_slots: int = 64, passes_per_step: int = 1, use_graph: bool = True,
                  capacity_bytes: int = 0, reserve_bytes: int = 0, planner_threads: int = 4,
-                 keep_states: bool = False, dry_run: bool = False, grid: int = 0, stream=None):
+                 keep_states: bool = False, dry_run: bool = False, grid: int = 0, stream=None,
+                 eps_tol: float = 0.0, norm_guard: float = 0.0):
         L = _bind()
         o = ServerOpts()
         o.capacity_bytes = capacity_bytes
@@ -76,6 +78,8 @@ class Server:
         o.planner_threads = planner_threads
         o.keep_states = 1 if keep_states else 0
         o.dry_run = 1 if dry_run else 0
+        o.eps_tol = eps_tol
+        o.norm_guard = norm_guard
         h = ctypes.c_void_p()
         sp = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
         Q.check(L.qsv_server_create(ctypes.byref(o), sp, ctypes.byref(h)))
@@ -86,7 +90,7 @@ class Server:
         gl = gates if isinstance(gates, (Q.GateList, Q.ArrayGateList)) else Q.GateList(gates)
         rid = ctypes.c_longlong()
         po = Q._opts(**plan_opts) if plan_opts else None
-        Q.check(_bind().qsv_server_submit(self.h, n, Q._DT[dtype], gl.arr, gl.n,
+        Q.check(_bind().qsv_server_submit(self.h, n, Q._DT_SERVE[dtype], gl.arr, gl.n,
                                           ctypes.byref(po) if po is not None else None, ctypes.byref(rid)))
         return rid.value
 
@@ -103,6 +107,7 @@ class Server:
             for k in range(c.value):
                 r = self._buf[k]
                 out.append({"id": r.id, "n": r.n, "dtype": "c64" if r.dtype == 0 else "c128", "status": r.status,
+                            "requested": ("c64", "c128", "auto")[r.requested], "promoted": bool(r.promoted),
                             "norm": r.norm, "zexp": np.array(r.zexp[: r.n]), "passes": r.passes, "fused": r.fused,
                             "t_submit": r.t_submit, "t_admit": r.t_admit, "t_finish": r.t_finish})
             if c.value < len(self._buf):

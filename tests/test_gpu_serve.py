@@ -138,3 +138,40 @@ def test_open_loop_stream_and_plain_path(mods):
     sv.close()
     plain = serve.run_plain(reqs[:8], circuits[:8])
     assert plain["completed"] == 8
+
+
+def test_auto_precision_and_norm_guard(mods):
+    """dtype "auto": the precision of Eq. 12 (small circuits complex64, large complex128)
+    and results against the oracle at that precision; with a norm guard that every
+    complex64 run fails, each of them is repeated in complex128 under the same id."""
+    qsv, serve = mods
+    rng = np.random.default_rng(8)
+    reqs = []
+    for _ in range(10):
+        n = int(rng.integers(6, 15))
+        reqs.append((n, C.brickwork(n, int(rng.integers(1, 6)), int(rng.integers(1 << 30)))))
+    reqs += [(16, C.brickwork(16, 40, 3)), (16, C.brickwork(16, 45, 4))]   # beyond Eq. 12's bound
+    for guard in (0.0, 1e-300):
+        sv = serve.Server(max_slots=8, norm_guard=guard)
+        ids = {sv.submit(n, "auto", ops): (n, ops) for n, ops in reqs}
+        res = drain(sv)
+        assert len(res) == len(reqs)
+        st = sv.stats()
+        promoted = 0
+        for r in res:
+            n, ops = ids[r["id"]]
+            chosen = qsv.precision_select(n, len(ops))
+            assert r["requested"] == "auto"
+            if guard > 0 and chosen == "c64":
+                # complex64 rounding always moves the norm a little away from 1
+                assert r["promoted"] and r["dtype"] == "c128"
+                promoted += 1
+            else:
+                assert not r["promoted"] and r["dtype"] == chosen
+            z, nrm, _ = zexp_oracle(n, ops)
+            tol = 1e-12 if r["dtype"] == "c128" else 5e-5
+            assert abs(r["norm"] - nrm) <= tol and np.max(np.abs(r["zexp"] - z)) <= tol
+        assert st["promoted"] == promoted
+        assert st["auto_c64"] + st["auto_c128"] == len(reqs)
+        assert st["auto_c64"] > 0 and st["auto_c128"] > 0
+        sv.close()

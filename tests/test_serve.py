@@ -68,3 +68,48 @@ def test_bad_circuit_is_an_argument_error():
     with pytest.raises(qsv.QSVError):
         sv.submit(4, "c64", [C.Op("H", (7,))])
     sv.close()
+
+
+# ------------------------------------------------------------------ adaptive precision (Eq. 11 / Eq. 12)
+
+def _paper(key):
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")) as f:
+        return json.load(f)[key]["value"]
+
+
+def test_precision_rule_reproduces_the_paper():
+    ex = _paper("precision_bound_example")
+    lhs = ex["g"] * 2 ** ex["n"] * 1.19e-7
+    assert round(lhs) == ex["lhs"]                              # "approximately 2.5 x 10^1"
+    assert qsv.precision_select(ex["n"], ex["g"]) == "c128"   # far above the threshold
+    limit = _paper("precision_c64_gate_limit_20q")
+    for g in (1, 10, limit - 1):
+        assert qsv.precision_select(20, g) == "c64"
+    for g in (limit, limit + 1, 200):
+        assert qsv.precision_select(20, g) == "c128"
+    # shallow moderate-width circuits (n <= 16, g < 50) stay in complex64
+    assert qsv.precision_select(16, 49) == "c64"
+    # an explicit tolerance moves the boundary: g * 2^n * 1.19e-7 <= tol
+    assert qsv.precision_select(10, 100, eps_tol=100 * 1024 * 1.19e-7 * 1.0001) == "c64"
+    assert qsv.precision_select(10, 100, eps_tol=100 * 1024 * 1.19e-7 * 0.9999) == "c128"
+    with pytest.raises(qsv.QSVError):
+        qsv.precision_select(0, 10)
+
+
+def test_auto_requests_follow_the_rule():
+    sv = Server(max_slots=8, dry_run=True, capacity_bytes=1 << 34)
+    want = {}
+    for n, depth in ((12, 2), (20, 2), (14, 10), (22, 1), (16, 3)):
+        ops = C.brickwork(n, depth, 1)
+        rid = sv.submit(n, "auto", ops)
+        want[rid] = qsv.precision_select(n, len(ops))
+    got = {r["id"]: r for r in drain(sv)}
+    assert set(got) == set(want)
+    for rid, dt in want.items():
+        assert got[rid]["dtype"] == dt and got[rid]["requested"] == "auto" and not got[rid]["promoted"]
+    st = sv.stats()
+    assert st["auto_c64"] == sum(v == "c64" for v in want.values())
+    assert st["auto_c128"] == sum(v == "c128" for v in want.values())
+    sv.close()
