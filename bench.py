@@ -19,8 +19,8 @@ complex-arithmetic FMA per amplitude / passes) x 2^n.  The average launch durati
 from HIP events recorded around every pass launch inside the timed steps, on the
 state's stream.  The bound reported is the larger fraction: HBM (8 TB/s) or ALU, whose
 peak combines the VALU rate for the VALU share of the FMA (78.6 TFLOP/s: FP64 vector,
-and FP32 without packed math) with the FP32 matrix-core rate (157.3 TFLOP/s) for the
-matrix-core share.  traffic = HBM bytes per launch measured with rocprofv3 counters
+and FP32 without packed math) with the matrix-core rate for the matrix-core share (FP32
+MFMA 157.3 TFLOP/s for complex64, FP64 MFMA 78.6 TFLOP/s for complex128).  traffic = HBM bytes per launch measured with rocprofv3 counters
 (FETCH_SIZE + WRITE_SIZE, scaled by the same counters' reading for a device copy of
 known size), taken from the summary under profiles/ when that summary was made from
 the current kernel source, else null.
@@ -47,6 +47,7 @@ HBM_PEAK_GBS = 8000.0
 # x 2 flops x 2.4 GHz = 78.6 TFLOP/s, which is also MI355X's FP64 vector peak.
 VALU_PEAK_TFLOPS = 78.6
 MFMA_FP32_PEAK_TFLOPS = 157.3
+MFMA_FP64_PEAK_TFLOPS = 78.6
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pass_brickwork30_hbm_traffic.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2604_03816_amd", "csrc", f) for f in ("kernels.hip", "planner.cpp")]
 
@@ -169,7 +170,8 @@ def run_dtype(torch, qsv, C, args, dtype, ops, terms):
     fma_v = (st["fma_per_amp"] - st["mfma_fma_per_amp"]) / st["passes"]
     fma_m = st["mfma_fma_per_amp"] / st["passes"]
     pass_flops = 2.0 * (fma_v + fma_m) * (2 ** n)
-    floor_s = 2.0 * (2 ** n) * (fma_v / (VALU_PEAK_TFLOPS * 1e12) + fma_m / (MFMA_FP32_PEAK_TFLOPS * 1e12))
+    mfma_peak = MFMA_FP32_PEAK_TFLOPS if dtype == "c64" else MFMA_FP64_PEAK_TFLOPS
+    floor_s = 2.0 * (2 ** n) * (fma_v / (VALU_PEAK_TFLOPS * 1e12) + fma_m / (mfma_peak * 1e12))
     alu_peak = pass_flops / floor_s / 1e12
     alu_tflops = pass_flops / (avg_pass_ms * 1e-3) / 1e12
     hbm_frac = achieved / HBM_PEAK_GBS

@@ -118,8 +118,10 @@ typedef struct {
     int low_qubits;      /* contiguous low qubits kept in every tile, 0 = default */
     double pass_budget;  /* per-pass arithmetic budget (FMA per amplitude), 0 = default,
                             < 0 = unlimited */
-    int matrix_cores;    /* complex64 dense ops on >= this many targets run on FP32 matrix
-                            cores (MFMA): 0 = default (3), -1 = never; in [3, 5] otherwise */
+    int matrix_cores;    /* dense ops on >= this many targets run on matrix cores (MFMA;
+                            FP32 for complex64, FP64 for complex128) when their operand
+                            block fits the pass's LDS budget: 0 = default (3), -1 = never;
+                            in [3, 5] otherwise */
 } qsv_plan_opts;
 
 typedef struct {
@@ -127,7 +129,8 @@ typedef struct {
     size_t fused_out;      /* fused gates after DAG fusion */
     size_t passes;         /* HBM passes (kernel launches) per application */
     size_t dense_ops, diag_ops, perm_ops;
-    size_t mfma_ops;       /* dense complex64 ops run on FP32 matrix cores */
+    size_t mfma_ops;       /* dense ops run on matrix cores (FP32 MFMA for complex64,
+                              FP64 MFMA for complex128) */
     double fma_per_amp;    /* complex-arithmetic cost summed over all passes */
     double hbm_bytes;      /* algorithmic HBM bytes per application = passes * 2 * 2^n * elem */
     double mfma_fma_per_amp;  /* the part of fma_per_amp done by the matrix-core ops */

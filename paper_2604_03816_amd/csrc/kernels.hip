@@ -241,21 +241,29 @@ __device__ void op_dense(C* __restrict__ lds, int T, const DevOp& op, cptr<C> __
     }
 }
 
-// Dense complex64 op on FP32 matrix cores.  The op is the real-embedded 2D x 2D matrix
-// (D = 2^K) times the tile viewed as D x (T / D) complex columns (one column per group of
-// amplitudes that differ only in the op's targets).  A wave takes 16 groups at a time:
-// lane (q, col) = (lane / 16, lane % 16) feeds group `col`, complex input rows 4 j + q
-// (real part, then imaginary part, as two K = 4 steps), and receives output rows
-// 8 rb + 2 q and 8 rb + 2 q + 1 of row block rb.  The A operands (host-arranged, see
-// the planner; staged in LDS once per kernel) stay in registers for the whole op.  All reads of a block precede its
-// writes, so the update is in place; waves own disjoint groups.
-template <int K>
-__device__ void op_dense_mfma(float2* __restrict__ lds, int T, const DevOp& op, const float* __restrict__ A)
+// Dense op on matrix cores: FP32 MFMA for complex64, FP64 MFMA for complex128.  The op
+// is the real-embedded 2D x 2D matrix (D = 2^K) times the tile viewed as D x (T / D)
+// complex columns (one column per group of amplitudes that differ only in the op's
+// targets).  A wave takes 16 groups at a time: lane (q, col) = (lane / 16, lane % 16)
+// feeds group `col`, complex input rows 4 j + q (real part, then imaginary part, as two
+// K = 4 steps), and receives output rows 8 rb + 2 q and 8 rb + 2 q + 1 of row block rb
+// (A[i][k] sits in lane i + 16 k and B[k][j] in lane j + 16 k in both precisions; the
+// output rows' order differs between the FP32 and FP64 instructions, which the planner's
+// arrangement of the A operand rows absorbs).  The A operands (staged in LDS once per
+// pass) stay in registers for the whole op.  All reads of a block precede its writes, so the update is in place; waves
+// own disjoint groups.
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <typename C, int K>
+__device__ void op_dense_mfma(C* __restrict__ lds, int T, const DevOp& op, const float* __restrict__ Araw)
 {
+    using R = typename std::conditional<sizeof(C) == 8, float, double>::type;
+    using Acc = typename std::conditional<sizeof(C) == 8, floatx4, doublex4>::type;
+    const R* __restrict__ A = reinterpret_cast<const R*>(Araw);
     constexpr int D = 1 << K, R2 = 2 * D, RB = R2 / 16, KS = R2 / 4;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int q = lane >> 4, col = lane & 15;
-    float a[RB][KS];
+    R a[RB][KS];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
@@ -273,22 +281,32 @@ __device__ void op_dense_mfma(float2* __restrict__ lds, int T, const DevOp& op, 
     const int bcol = group_base<K>(col, op);
     for (int blk = wave; blk < nblk; blk += kThreads / 64) {
         const int sb = group_base<K>(blk << 4, op) | bcol;
-        floatx4 acc[RB];
+        Acc acc[RB];
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb) acc[rb] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int rb = 0; rb < RB; ++rb) acc[rb] = Acc{0, 0, 0, 0};
 #pragma unroll
         for (int j = 0; j < KS / 2; ++j) {
-            const float2 v = lds[sb | rin[j]];
+            const C v = lds[sb | rin[j]];
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) {
-                acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][2 * j], v.x, acc[rb], 0, 0, 0);
-                acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][2 * j + 1], v.y, acc[rb], 0, 0, 0);
+                if constexpr (sizeof(C) == 8) {
+                    acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][2 * j], v.x, acc[rb], 0, 0, 0);
+                    acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][2 * j + 1], v.y, acc[rb], 0, 0, 0);
+                } else {
+                    acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb][2 * j], v.x, acc[rb], 0, 0, 0);
+                    acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb][2 * j + 1], v.y, acc[rb], 0, 0, 0);
+                }
             }
         }
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
-            lds[sb | rout[2 * rb]] = make_float2(acc[rb][0], acc[rb][1]);
-            lds[sb | rout[2 * rb + 1]] = make_float2(acc[rb][2], acc[rb][3]);
+            C o0, o1;
+            o0.x = acc[rb][0];
+            o0.y = acc[rb][1];
+            o1.x = acc[rb][2];
+            o1.y = acc[rb][3];
+            lds[sb | rout[2 * rb]] = o0;
+            lds[sb | rout[2 * rb + 1]] = o1;
         }
     }
 }
@@ -342,16 +360,13 @@ __device__ __forceinline__ void apply_ops(C* __restrict__ lds, int T, cptr<DevOp
     for (int oi = 0; oi < op_count; ++oi) {
         const DevOp op = ops[op_begin + oi];
         cptr<C> M = pool + op.off;
-        if constexpr (std::is_same<C, float2>::value) {
-            if (op.kind == OP_DENSE && op.aoff >= 0) {
-                const float* Am = alds + op.aoff;
-                // the planner gives matrix cores 3- and 4-qubit ops only (a 5-qubit
-                // operand block exceeds the per-pass LDS operand budget)
-                if (op.k == 3) op_dense_mfma<3>(lds, T, op, Am);
-                else op_dense_mfma<4>(lds, T, op, Am);
-                __syncthreads();
-                continue;
-            }
+        if (op.kind == OP_DENSE && op.aoff >= 0) {
+            // the planner gives matrix cores 3- and 4-qubit ops only (a 5-qubit operand
+            // block exceeds the per-pass LDS operand budget)
+            if (op.k == 3) op_dense_mfma<C, 3>(lds, T, op, alds + op.aoff);
+            else op_dense_mfma<C, 4>(lds, T, op, alds + op.aoff);
+            __syncthreads();
+            continue;
         }
         if (op.kind == OP_DENSE) {
             switch (op.k) {
@@ -1033,7 +1048,8 @@ hipError_t launch_pass_t(void* st, const PassArgs& a, long long ntiles, const De
     using C = typename CT<R>::T;
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_pass<C>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+        // a 64 KiB complex128 tile plus its operand block exceeds the 64 KiB default
+        hipError_t e = hipFuncSetAttribute((const void*)k_pass<C>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
@@ -1046,8 +1062,9 @@ hipError_t launch_pass_t(void* st, const PassArgs& a, long long ntiles, const De
 hipError_t launch_batch_pass(int dtype, const BatchItem* items, const int* count, int grid, int tile_qubits,
                              hipStream_t s)
 {
+    // tile + the per-pass operand block (MFMA matrices, diagonal tables) of either dtype
     const size_t lds = ((dtype == 0 ? sizeof(float2) : sizeof(double2)) << tile_qubits) +
-                       (dtype == 0 ? sizeof(float) * kServeOperandFloats : 0);
+                       sizeof(float) * kServeOperandFloats;
     if (dtype == 0) {
         static bool set = false;
         if (!set) {

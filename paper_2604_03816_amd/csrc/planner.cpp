@@ -52,12 +52,15 @@ PlanOpts default_opts(int dtype)
         o.pass_budget = 160;
         o.sigma = 8;
         o.mfma_min_k = 3;
+        o.fp32_mfma = true;
     } else {            // complex128: 16-byte amplitudes
         o.tile_qubits = 12;
         o.low_qubits = 4;
         o.whole_state_max = 12;
         o.pass_budget = 448;
         o.sigma = 8;
+        o.mfma_min_k = 3;          // FP64 matrix cores: no faster than FP64 VALU in peak,
+        o.mfma_lds_floats = 4096;  // but free of the VALU path's per-row scalar loads
     }
     return o;
 }
@@ -121,26 +124,30 @@ double op_fma(const FGate& g)
 double op_cost(const FGate& g, const PlanOpts& o)
 {
     const double f = op_fma(g);
-    if (g.kind == OP_DENSE && o.mfma_min_k > 0 && g.k >= o.mfma_min_k) return 0.5 * f;
+    if (g.kind == OP_DENSE && o.fp32_mfma && o.mfma_min_k > 0 && g.k >= o.mfma_min_k) return 0.5 * f;
     return f;
 }
 
 namespace {
 
 // Real-embedded 2D x 2D matrix of a dense complex D x D op, laid out as the A operands
-// of 16x16x4 FP32 MFMA steps: entry ((rb * KS + ks) * 64 + lane) is A[16 rb + lane % 16]
-// [4 ks + lane / 16].  Output row I <-> (element I / 2, real/imag I % 2); input column
-// kk <-> (element 4 (kk / 8) + kk % 4, real/imag (kk / 4) % 2), the order in which the
-// kernel feeds each lane's complex inputs.
-std::vector<float> mfma_operand(const std::vector<cd>& m, int k)
+// of 16x16x4 MFMA steps: entry ((rb * KS + ks) * 64 + lane) is A[16 rb + i][4 ks + lane
+// / 16] with i = lane % 16.  Input column kk <-> (element 4 (kk / 8) + kk % 4, real/imag
+// (kk / 4) % 2), the order in which the kernel feeds each lane's complex inputs.  Output
+// rows are ordered so that output element e of lane q * 16 + col is (complex row 8 rb +
+// 2 q + e / 2, real/imag e % 2) in both precisions: the FP32 instruction returns row i
+// = 4 q + e there, so row i <-> (i / 2, i % 2); the FP64 instruction returns row i = 4 e
+// + q (measured on gfx950), so row i <-> (2 (i % 4) + i / 8, (i / 4) % 2).
+std::vector<double> mfma_operand(const std::vector<cd>& m, int k, bool fp64)
 {
     const int D = 1 << k, R2 = 2 * D, RB = R2 / 16, KS = R2 / 4;
-    std::vector<float> out((size_t)R2 * R2);
+    std::vector<double> out((size_t)R2 * R2);
     for (int rb = 0; rb < RB; ++rb)
         for (int ks = 0; ks < KS; ++ks)
             for (int lane = 0; lane < 64; ++lane) {
-                const int I = 16 * rb + lane % 16, kk = 4 * ks + lane / 16;
-                const int ro = I / 2, co = I % 2;
+                const int i = lane % 16, kk = 4 * ks + lane / 16;
+                const int ro = 8 * rb + (fp64 ? 2 * (i % 4) + i / 8 : i / 2);
+                const int co = fp64 ? (i / 4) % 2 : i % 2;
                 const int ri = 4 * (kk / 8) + kk % 4, ci = (kk / 4) % 2;
                 const cd u = m[(size_t)ro * D + ri];
                 double v;
@@ -148,7 +155,7 @@ std::vector<float> mfma_operand(const std::vector<cd>& m, int k)
                 else if (co == 0 && ci == 1) v = -u.imag();
                 else if (co == 1 && ci == 0) v = u.imag();
                 else v = u.real();
-                out[(size_t)(rb * KS + ks) * 64 + lane] = (float)v;
+                out[(size_t)(rb * KS + ks) * 64 + lane] = v;
             }
     return out;
 }
@@ -541,13 +548,26 @@ bool make_plan(int n, int dtype, const std::vector<InGate>& gates, const PlanOpt
             if (g.kind == OP_DENSE) {
                 P.pool.insert(P.pool.end(), g.m.begin(), g.m.end());
                 ++P.dense_ops;
-                const int af = 4 << (2 * g.k);   // (2 * 2^k)^2 floats
+                // (2 * 2^k)^2 operand entries: FP32 for complex64, FP64 (two floats' worth
+                // of bits each, 16-byte aligned) for complex128
+                const int per = dtype == 0 ? 1 : 2;
+                const int af = per * (4 << (2 * g.k));
+                const int at = (a.a_len + 3) & ~3;
                 if (o.mfma_min_k > 0 && g.k >= o.mfma_min_k && (1 << (a.m - g.k)) >= 16 &&
-                    a.a_len + af <= o.mfma_lds_floats) {
-                    const std::vector<float> A = mfma_operand(g.m, g.k);
-                    d.aoff = a.a_len;
-                    P.apool.insert(P.apool.end(), A.begin(), A.end());
-                    a.a_len += af;
+                    at + af <= o.mfma_lds_floats) {
+                    const std::vector<double> A = mfma_operand(g.m, g.k, dtype != 0);
+                    P.apool.resize((size_t)a.a_off + at, 0.0f);
+                    d.aoff = at;
+                    for (const double v : A) {
+                        if (dtype == 0) {
+                            P.apool.push_back((float)v);
+                        } else {
+                            float w[2];
+                            std::memcpy(w, &v, 8);
+                            P.apool.insert(P.apool.end(), w, w + 2);
+                        }
+                    }
+                    a.a_len = at + af;
                     ++P.mfma_ops;
                     P.mfma_fma_per_amp += op_fma(g);
                 }

@@ -40,7 +40,8 @@ struct PlanOpts {
     double pass_budget = 160;  // FMA per amplitude per pass (<0: unlimited)
     double sigma = 8;          // per-op on-chip cost in FMA-per-amplitude units
     int max_ops_per_pass = 0;  // 0: no limit
-    int mfma_min_k = 0;        // dense ops with k >= this run on MFMA (complex64 only); 0: never
+    int mfma_min_k = 0;        // dense ops with k >= this run on MFMA; 0: never
+    bool fp32_mfma = false;    // complex64: MFMA at twice the VALU rate (cost halved in planning)
     int mfma_lds_floats = 2048;  // per-pass cap of operand floats staged in LDS (MFMA matrices,
                                  // diagonal tables)
 };
@@ -82,8 +83,9 @@ bool plan_opts_from(int dtype, const qsv_plan_opts* pub, PlanOpts& o, std::strin
 // or 4 with phases).
 double op_fma(const FGate& g);
 
-// Scheduling cost of one op on chip (excluding sigma): op_fma, halved for dense ops that
-// run on FP32 MFMA (twice the non-packed VALU rate).
+// Scheduling cost of one op on chip (excluding sigma): op_fma, halved for complex64 dense
+// ops that run on FP32 MFMA (twice the non-packed VALU rate; FP64 MFMA has the FP64 VALU
+// rate, so complex128 costs are unchanged).
 double op_cost(const FGate& g, const PlanOpts& o);
 
 // Classifies a dense matrix: OP_DIAG when every off-diagonal entry is exactly zero,

@@ -175,3 +175,26 @@ def test_auto_precision_and_norm_guard(mods):
         assert st["auto_c64"] + st["auto_c128"] == len(reqs)
         assert st["auto_c64"] > 0 and st["auto_c128"] > 0
         sv.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_served_circuits_with_diagonal_and_permutation_ops(mods, dtype):
+    """QFT (controlled phases: diagonal tables staged with the pass) and circuits with
+    SWAP / Toffoli (permutations) through the batched kernel."""
+    qsv, serve = mods
+    sv = serve.Server(max_slots=8)
+    reqs = [(n, C.qft(n)) for n in (8, 12, 15)]
+    rng = np.random.default_rng(5)
+    for n in (9, 14):
+        ops = C.brickwork(n, 4, int(rng.integers(1 << 30)))
+        ops += [C.Op("SWAP", (0, n - 1)), C.Op("TOFFOLI", (1, n - 2, 3)), C.Op("CZ", (2, n - 3)), C.Op("T", (n - 1,))]
+        reqs.append((n, ops))
+    ids = {sv.submit(n, dtype, ops): (n, ops) for n, ops in reqs}
+    res = drain(sv)
+    assert len(res) == len(reqs)
+    for r in res:
+        n, ops = ids[r["id"]]
+        z, nrm, _ = zexp_oracle(n, ops)
+        tol = 1e-12 if dtype == "c128" else 5e-5
+        assert r["status"] == 0 and abs(r["norm"] - nrm) <= tol and np.max(np.abs(r["zexp"] - z)) <= tol
+    sv.close()
