@@ -262,3 +262,32 @@ def test_circuit_then_inverse_is_identity_24q(qsv, dtype):
     tol = 1e-12 if dtype == "c128" else 2e-5
     assert abs(got[0] - 1) <= tol
     assert np.max(np.abs(got[1:])) <= tol
+
+
+@pytest.mark.parametrize("n,dtype", [(33, "c64"), (34, "c64"), (32, "c128")])
+def test_maximum_sizes_circuit_then_inverse(qsv, n, dtype):
+    """The largest states the ABI accepts (34 qubits: 128 GiB in complex64) and the
+    largest complex128 state the precision study uses (32 qubits, 64 GiB): a random
+    brickwork and its inverse return |0...0> (checked on the device through the norm, a
+    marginal and sampling, without copying the state to the host)."""
+    import torch
+    ops = C.brickwork(n, 3, 40 + n)
+    s = qsv.State(n, dtype)
+    s.apply(ops)
+    tol = 1e-12 if dtype == "c128" else 1e-5
+    assert abs(s.norm() - 1) <= tol
+    s.apply(C.inverse_ops(ops))
+    p = s.probs([0, n // 2, n - 1])
+    assert abs(p[0] - 1) <= 10 * tol and np.max(np.abs(p[1:])) <= 10 * tol
+    assert np.all(s.sample(np.linspace(0.0, 0.999, 64)) == 0)
+    s.free()
+    torch.cuda.empty_cache()
+
+
+def test_empty_inputs(qsv):
+    s = qsv.State(12, "c64")
+    s.apply([])                                   # empty circuit: nothing to do
+    assert abs(s.expval([]) - 0.0) == 0.0         # empty Pauli sum
+    assert s.sample(np.zeros(0)).size == 0        # no shots
+    assert abs(s.norm() - 1) < 1e-7
+    s.free()
