@@ -664,26 +664,53 @@ __device__ __forceinline__ void expval_tiles(gptr<C> __restrict__ sa, gptr<C> __
                 const int q = __builtin_amdgcn_readfirstlane(rows[i].q);
                 const long long g = rows[i].g;
                 const int zhi = z >> kLogThreads;
-                const bool neg = (__popc(tid & z & (kThreads - 1)) + __popcll(base & g)) & 1;
+                const bool gneg = __popcll(base & g) & 1;                  // bits outside the tile
+                const bool tneg = __popc(tid & z & (kThreads - 1)) & 1;   // bits of the thread id
                 double val;
                 if (x == 0) {
                     const int w = (zhi << kLogThreads) + tid;
                     const double r = wre[w], m = TWO ? wim[w] : 0.0;
                     val = (q == 0) ? r : (q == 1) ? -m : (q == 2) ? -r : m;
+                    if (tneg) val = -val;
+                } else if (!TWO) {
+                    // <a|P|a> over pairs (e, e ^ x), e with x's lowest bit clear: with
+                    // w = conj(a[e ^ x]) a[e] the pair adds s(e) i^q (w + (-1)^{|x & z|}
+                    // conj(w)), whose real part is 2 Re(i^q w) when |x & z| is even and
+                    // 2 Re(i^(q+1) Im(w)) when it is odd: half the elements, one product
+                    const int lb = __ffs(x) - 1;
+                    const bool odd = __popc(x & z) & 1;
+                    val = 0.0;
+                    for (int p0 = 0; p0 < (NS << (kLogThreads - 1)); p0 += kThreads) {
+                        const int pr = p0 + tid;
+                        const int e = ((pr >> lb) << (lb + 1)) | (pr & ((1 << lb) - 1));
+                        const C ap = tla[e ^ x];
+                        const C ae = tla[e];
+                        double v;
+                        if (!odd) {
+                            const double re = (double)ap.x * (double)ae.x + (double)ap.y * (double)ae.y;
+                            v = (q == 0) ? re : (q == 2) ? -re : 0.0;
+                        } else {
+                            const double im = (double)ap.x * (double)ae.y - (double)ap.y * (double)ae.x;
+                            v = (q == 1) ? -im : (q == 3) ? im : 0.0;
+                        }
+                        val += (__popc(e & z) & 1) ? -v : v;
+                    }
+                    val *= 2.0;
                 } else {
                     val = 0.0;
 #pragma unroll 4
                     for (int j = 0; j < NS; ++j) {
                         const int e = (j << kLogThreads) | tid;
                         const C ap = tla[e ^ x];
-                        const C be = TWO ? tlb[e] : tla[e];
+                        const C be = tlb[e];
                         const double pr = (double)ap.x * (double)be.x + (double)ap.y * (double)be.y;
                         const double pi = (double)ap.x * (double)be.y - (double)ap.y * (double)be.x;
                         const double v = (q == 0) ? pr : (q == 1) ? -pi : (q == 2) ? -pr : pi;
                         val += (__popc(j & zhi) & 1) ? -v : v;
                     }
+                    if (tneg) val = -val;
                 }
-                acc[i] += neg ? -val : val;
+                acc[i] += gneg ? -val : val;
             }
         }
         __syncthreads();   // the next tile overwrites LDS
