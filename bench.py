@@ -68,6 +68,7 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-sampling", action="store_true")
     ap.add_argument("--no-noise", action="store_true")
+    ap.add_argument("--no-commute", action="store_true")
     ap.add_argument("--precision-qubits", type=int, nargs="*", default=[30, 32])
     ap.add_argument("--adjoint-qubits", type=int, default=24)
     ap.add_argument("--adjoint-batch", type=int, default=64)
@@ -308,6 +309,45 @@ def precision_study(args):
     return out
 
 
+def commutation_bench(args):
+    """Commutation-aware DAG (ops diagonal on every qubit they share left unordered, so
+    fusion and pass scheduling may cross them) against the per-qubit DAG, on the
+    30-qubit H/T + CZ bricks (depth 20, seed 2) and on the main step's brickwork:
+    fused ops, passes and the time of one application (median of 3), per precision."""
+    import torch
+    from paper_2604_03816_amd import circuits as C
+    from paper_2604_03816_amd import qsv
+    n = args.qubits
+    circuits = {"h_t_cz_bricks depth=20 seed=2": C.h_t_cz_bricks(n, 20, 2),
+                "brickwork depth=%d seed=%d" % (args.depth, args.seed): C.brickwork(n, args.depth, args.seed)}
+    out = {}
+    for dt in ("c64", "c128"):
+        s = qsv.State(n, dt)
+        for name, ops in circuits.items():
+            rec = {}
+            for label, commute in (("per_qubit_dag", -1), ("commutation_dag", 1)):
+                t0 = time.perf_counter()
+                plan = qsv.Plan(n, dt, ops, commute=commute)
+                plan_ms = (time.perf_counter() - t0) * 1e3
+                ts = []
+                for _ in range(3):
+                    s.reset()
+                    s.sync()
+                    t0 = time.perf_counter()
+                    s.apply_plan(plan)
+                    s.sync()
+                    ts.append((time.perf_counter() - t0) * 1e3)
+                st = plan.stats()
+                rec[label] = {"fused": st["fused_out"], "passes": st["passes"], "plan_ms": plan_ms,
+                              "apply_ms": sorted(ts)[1]}
+                plan.free()
+            rec["speedup"] = rec["per_qubit_dag"]["apply_ms"] / rec["commutation_dag"]["apply_ms"]
+            out["%s %s" % (name, dt)] = rec
+        s.free()
+        torch.cuda.empty_cache()
+    return out
+
+
 def adjoint_bench(args):
     """Adjoint gradients: 24-qubit ansatz, 8 layers of RY, RZ + CZ ring (384 parameters),
     transverse-field Ising H (periodic, h = 0.7), 64 parameter vectors; complex128 and
@@ -461,6 +501,8 @@ def main():
         rec["sampling"] = sampling_bench(args, ops)
     if not args.no_noise:
         rec["noise"] = noise_bench(args)
+    if not args.no_commute:
+        rec["commutation"] = commutation_bench(args)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(C, args, ops)
     print(json.dumps(rec))

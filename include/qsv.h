@@ -122,6 +122,11 @@ typedef struct {
                             FP32 for complex64, FP64 for complex128) when their operand
                             block fits the pass's LDS budget: 0 = default (3), -1 = never;
                             in [3, 5] otherwise */
+    int commute;         /* fuse = 1 only.  1 (default): commutation-aware DAG -- ops that
+                            are diagonal on every qubit they share are left unordered, so
+                            fusion may merge them across one another and a pass may take
+                            such an op ahead of deferred ones; -1: the per-qubit DAG of
+                            Section 5.1 exactly */
 } qsv_plan_opts;
 
 typedef struct {

@@ -29,7 +29,7 @@ import numpy as np
 __all__ = [
     "Op", "haar_u2", "brickwork", "brickwork_arrays", "ghz", "hea", "hea_params", "qft", "random_1q",
     "tfim_terms", "zz_chain_terms", "x_sum_terms", "bind", "inverse_ops",
-    "serving_stream", "Request", "with_depolarizing", "CHANNELS",
+    "serving_stream", "Request", "with_depolarizing", "CHANNELS", "h_t_cz_bricks", "commuting_mix",
 ]
 
 CHANNELS = ("DEPOLARIZE", "AMPDAMP")
@@ -166,6 +166,57 @@ def random_1q(n: int, seed: int, gates_per_qubit: int = 10) -> List[Op]:
     for _ in range(gates_per_qubit * n):
         q = int(rng.integers(0, n))
         ops.append(Op("U", (q,), matrix=haar_u2(rng)))
+    return ops
+
+
+def h_t_cz_bricks(n: int, depth: int, seed: int) -> List[Op]:
+    """Layers of H or T on every qubit (a coin flip each) followed by CZ bricks (2i, 2i+1)
+    on even layers and (2i+1, 2i+2) on odd ones.  T and CZ are diagonal, so long stretches
+    of the circuit commute although they share qubits."""
+    rng = np.random.default_rng(seed)
+    ops: List[Op] = []
+    for layer in range(depth):
+        for q in range(n):
+            ops.append(Op("T" if rng.random() < 0.5 else "H", (q,)))
+        for q in range(layer % 2, n - 1, 2):
+            ops.append(Op("CZ", (q, q + 1)))
+    return ops
+
+
+def _haar(rng: np.random.Generator, d: int) -> np.ndarray:
+    z = rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d))
+    q, r = np.linalg.qr(z)
+    return q * (np.diag(r) / np.abs(np.diag(r)))
+
+
+def commuting_mix(n: int, count: int, seed: int) -> List[Op]:
+    """Random gates many of which are diagonal on some of their qubits: random phases on
+    1-3 qubits (20%), CZ / CNOT / TOFFOLI on random qubits (40%), controlled Haar
+    unitaries on 2-3 qubits with the control on local bit 0 (15%), Haar U(2) / U(4)
+    (25%).  Ops of the first three kinds commute whenever each shared qubit is a phase
+    or control qubit of both."""
+    rng = np.random.default_rng(seed)
+    ops: List[Op] = []
+    for _ in range(count):
+        r = rng.random()
+        if r < 0.2:
+            k = int(rng.integers(1, 4))
+            qs = tuple(int(q) for q in rng.permutation(n)[:k])
+            ops.append(Op("U", qs, matrix=np.diag(np.exp(1j * rng.uniform(0, 2 * math.pi, 1 << k)))))
+        elif r < 0.6:
+            name, k = [("CZ", 2), ("CNOT", 2), ("TOFFOLI", 3)][int(rng.integers(0, 3))]
+            ops.append(Op(name, tuple(int(q) for q in rng.permutation(n)[:k])))
+        elif r < 0.75:
+            k = int(rng.integers(2, 4))
+            qs = tuple(int(q) for q in rng.permutation(n)[:k])
+            u = _haar(rng, 1 << (k - 1))
+            m = np.zeros((1 << k, 1 << k), complex)
+            m[0::2, 0::2] = np.eye(1 << (k - 1))   # control (local bit 0) clear: identity
+            m[1::2, 1::2] = u                       # control set: u on the other targets
+            ops.append(Op("U", qs, matrix=m))
+        else:
+            k = int(rng.integers(1, 3))
+            ops.append(Op("U", tuple(int(q) for q in rng.permutation(n)[:k]), matrix=_haar(rng, 1 << k)))
     return ops
 
 

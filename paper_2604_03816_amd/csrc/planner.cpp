@@ -83,6 +83,9 @@ bool plan_opts_from(int dtype, const qsv_plan_opts* pub, PlanOpts& o, std::strin
         }
         o.mfma_min_k = pub->matrix_cores < 0 ? 0 : pub->matrix_cores;
     }
+    if (pub->commute < -1 || pub->commute > 1) { err = "commute must be 0, 1 or -1"; return false; }
+    if (pub->commute) o.commute = pub->commute > 0;
+    if (o.fuse != 1) o.commute = 0;
     if (o.fuse == 0) o.max_ops_per_pass = 1;
     return true;
 }
@@ -105,6 +108,29 @@ int classify(const std::vector<cd>& m, int k)
     for (int c = 0; c < d; ++c)
         if (colcount[c] != 1) return OP_DENSE;
     return OP_PERM;
+}
+
+unsigned long long diag_qubit_mask(const FGate& g)
+{
+    const int d = 1 << g.k;
+    unsigned long long dq = 0;
+    for (int j = 0; j < g.k; ++j) {
+        bool diag = true;
+        for (int r = 0; r < d && diag; ++r)
+            for (int c = 0; c < d; ++c)
+                if (((r ^ c) >> j) & 1 && g.m[(size_t)r * d + c] != cd(0, 0)) { diag = false; break; }
+        if (diag) dq |= 1ull << g.q[j];
+    }
+    return dq;
+}
+
+bool ops_commute(const FGate& a, const FGate& b)
+{
+    unsigned long long qa = 0, qb = 0;
+    for (int j = 0; j < a.k; ++j) qa |= 1ull << a.q[j];
+    for (int j = 0; j < b.k; ++j) qb |= 1ull << b.q[j];
+    const unsigned long long shared = qa & qb;
+    return (shared & ~(a.dq & b.dq)) == 0;
 }
 
 double op_fma(const FGate& g)
@@ -226,6 +252,7 @@ FGate canonical(const InGate& g, int index)
     for (int r = 0; r < d; ++r)
         for (int c = 0; c < d; ++c) f.m[(size_t)r * d + c] = g.m[(size_t)remap(r) * d + remap(c)];
     f.kind = classify(f.m, f.k);
+    f.dq = diag_qubit_mask(f);
     f.first = index;
     return f;
 }
@@ -305,6 +332,7 @@ FGate fuse_pair(const FGate& u, const FGate& v, int kmax, bool& ok)
     const std::vector<cd> ev = embed(v.m, v.q, v.k, Q, kq);
     f.m = matmul(ev, eu, d);  // Eq. 9: U_fused = U_v . U_u (u applied first)
     f.kind = classify(f.m, kq);
+    f.dq = diag_qubit_mask(f);
     f.first = std::min(u.first, v.first);
     f.members = u.members + v.members;
     return f;
@@ -414,6 +442,267 @@ void run_fusion(std::vector<Node>& nodes, const PlanOpts& o)
     }
 }
 
+// ---- commutation-aware DAG and fusion (option commute)
+//
+// Two ops commute when they are both diagonal on every qubit they share, so among the
+// ops touching a qubit q only the order between a run of ops diagonal on q and the op
+// not diagonal on q that ends the run matters.  The DAG below keeps exactly those
+// per-qubit edges: an op diagonal on q depends on the last op not diagonal on q; an op
+// not diagonal on q depends on every op of the diagonal run before it (or, without
+// one, on the previous op not diagonal on q).  Every pair of ops that may not commute
+// is then joined by a path, so any topological order applies the circuit's operator.
+//
+// Fusion follows the sweep of Algorithm 2 on this DAG.  Its candidates for v are v's
+// DAG predecessors and, on each qubit of v, the nearest earlier ops that commute with v
+// there (they have no edge to v: a diagonal run); a merge needs the width bound, rule
+// A or rule B (either one rules out any path u ~> v besides a direct edge, which also
+// makes u and v commute when they have no edge, so the product order U_v . U_u is
+// right either way) and, in cost-aware mode, the arithmetic condition.
+struct CNode {
+    FGate g;
+    bool alive = true;
+    unsigned long long qm = 0;
+    std::vector<int> pred, succ;
+};
+
+unsigned long long qubit_mask(const FGate& g)
+{
+    unsigned long long m = 0;
+    for (int j = 0; j < g.k; ++j) m |= 1ull << g.q[j];
+    return m;
+}
+
+void add_edge(std::vector<CNode>& N, int a, int b)
+{
+    if (a < 0 || a == b) return;
+    std::vector<int>& s = N[a].succ;
+    if (std::find(s.begin(), s.end(), b) != s.end()) return;
+    s.push_back(b);
+    N[b].pred.push_back(a);
+}
+
+// Kahn's algorithm over the edge lists; ties broken by the smallest member index.
+std::vector<int> topo_order_dag(const std::vector<CNode>& N)
+{
+    const int G = (int)N.size();
+    std::vector<int> indeg(G, 0);
+    using Item = std::pair<int, int>;
+    std::priority_queue<Item, std::vector<Item>, std::greater<Item>> ready;
+    for (int i = 0; i < G; ++i) {
+        if (!N[i].alive) continue;
+        indeg[i] = (int)N[i].pred.size();
+        if (indeg[i] == 0) ready.push({N[i].g.first, i});
+    }
+    std::vector<int> order;
+    order.reserve(G);
+    while (!ready.empty()) {
+        const int u = ready.top().second;
+        ready.pop();
+        order.push_back(u);
+        for (const int s : N[u].succ)
+            if (--indeg[s] == 0) ready.push({N[s].g.first, s});
+    }
+    return order;
+}
+
+// In node x's list, replace `from` by `to` (dropping `from` when `to` is already there).
+void relink(std::vector<int>& lst, int from, int to)
+{
+    const bool has_to = std::find(lst.begin(), lst.end(), to) != lst.end();
+    for (size_t i = 0; i < lst.size(); ++i) {
+        if (lst[i] != from) continue;
+        if (has_to) lst.erase(lst.begin() + (long)i);
+        else lst[i] = to;
+        return;
+    }
+}
+
+std::vector<FGate> fuse_commuting(const std::vector<FGate>& gates, int n, const PlanOpts& o, bool diag_only)
+{
+    const int G = (int)gates.size();
+    std::vector<CNode> N(G);
+    {
+        std::vector<int> last_nd(n, -1);
+        std::vector<std::vector<int>> run(n);
+        for (int i = 0; i < G; ++i) {
+            N[i].g = gates[i];
+            N[i].qm = qubit_mask(gates[i]);
+            for (int j = 0; j < gates[i].k; ++j) {
+                const int q = gates[i].q[j];
+                if ((gates[i].dq >> q) & 1) {
+                    add_edge(N, last_nd[q], i);
+                    run[q].push_back(i);
+                } else {
+                    if (run[q].empty()) add_edge(N, last_nd[q], i);
+                    for (const int r : run[q]) add_edge(N, r, i);
+                    run[q].clear();
+                    last_nd[q] = i;
+                }
+            }
+        }
+    }
+    constexpr int kWindow = 8;   // commuting candidates examined per qubit of v
+    std::vector<int> pos(G, 0);
+    std::vector<std::vector<int>> lines(n);
+    std::vector<int> at((size_t)G * kMaxK, -1), atq((size_t)G * kMaxK, -1);
+    bool changed = true;
+    while (changed) {
+        changed = false;
+        const std::vector<int> order = topo_order_dag(N);
+        for (int i = 0; i < (int)order.size(); ++i) pos[order[i]] = i;
+        // per-qubit lists of the live ops in this sweep's order
+        for (auto& l : lines) l.clear();
+        for (const int v : order)
+            for (int j = 0; j < N[v].g.k; ++j) {
+                const int q = N[v].g.q[j];
+                atq[(size_t)v * kMaxK + j] = q;
+                at[(size_t)v * kMaxK + j] = (int)lines[q].size();
+                lines[q].push_back(v);
+            }
+        const std::vector<int> snapshot_k = [&] {
+            std::vector<int> k(G, 0);
+            for (const int v : order) k[v] = N[v].g.k;
+            return k;
+        }();
+        std::vector<int> cand;
+        for (const int v : order) {
+            if (!N[v].alive) continue;
+            cand.assign(N[v].pred.begin(), N[v].pred.end());
+            for (int j = 0; j < snapshot_k[v]; ++j) {
+                const int q = atq[(size_t)v * kMaxK + j];
+                const std::vector<int>& line = lines[q];
+                int seen = 0;
+                for (int t = at[(size_t)v * kMaxK + j] - 1; t >= 0 && seen < kWindow; --t) {
+                    const int u = line[t];
+                    if (!N[u].alive || u == v || !((N[u].qm >> q) & 1)) continue;
+                    ++seen;
+                    cand.push_back(u);
+                    if (!ops_commute(N[u].g, N[v].g)) break;   // ops further back are ordered before u
+                }
+            }
+            std::sort(cand.begin(), cand.end());
+            cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+            std::sort(cand.begin(), cand.end(), [&](int a, int b) { return pos[a] > pos[b]; });
+            for (const int u : cand) {
+                CNode& U = N[u];
+                CNode& V = N[v];
+                if (!U.alive || u == v || pos[u] >= pos[v] || !(U.qm & V.qm)) continue;
+                if (diag_only && (U.g.kind != OP_DIAG || V.g.kind != OP_DIAG)) continue;
+                const int kq = __builtin_popcountll(U.qm | V.qm);
+                if (kq > o.kmax) continue;
+                bool ruleA = true, ruleB = true;
+                for (const int p : V.pred)
+                    if (p != u && pos[p] > pos[u]) { ruleA = false; break; }
+                for (const int sx : U.succ)
+                    if (sx != v && pos[sx] < pos[v]) { ruleB = false; break; }
+                if (!ruleA && !ruleB) continue;
+                if (o.cost_aware > 0 && (U.g.kind == OP_DENSE || V.g.kind == OP_DENSE)) {
+                    FGate probe;
+                    probe.k = kq;
+                    probe.kind = OP_DENSE;
+                    if (op_cost(probe, o) > op_cost(U.g, o) + op_cost(V.g, o) + o.sigma) continue;
+                }
+                bool ok = false;
+                FGate f = fuse_pair(U.g, V.g, o.kmax, ok);
+                if (!ok) continue;
+                if (o.cost_aware > 0 && op_cost(f, o) > op_cost(U.g, o) + op_cost(V.g, o) + o.sigma) continue;
+                // merge v into u: u takes v's edges
+                for (const int p : V.pred) {
+                    if (p == u) continue;
+                    relink(N[p].succ, v, u);
+                    if (std::find(U.pred.begin(), U.pred.end(), p) == U.pred.end()) U.pred.push_back(p);
+                }
+                for (const int sx : V.succ) {
+                    relink(N[sx].pred, v, u);
+                    if (std::find(U.succ.begin(), U.succ.end(), sx) == U.succ.end()) U.succ.push_back(sx);
+                }
+                U.succ.erase(std::remove(U.succ.begin(), U.succ.end(), v), U.succ.end());
+                U.g = std::move(f);
+                U.qm = qubit_mask(U.g);
+                V.alive = false;
+                V.pred.clear();
+                V.succ.clear();
+                if (!ruleA) pos[u] = pos[v];   // rule B: the fused op takes v's slot
+                changed = true;
+                break;
+            }
+        }
+    }
+    std::vector<FGate> out;
+    for (const int v : topo_order_dag(N)) out.push_back(N[v].g);
+    return out;
+}
+
+// Pass scheduling: greedy grouping of the fused ops (in their order) into HBM passes.
+bool schedule_passes(int n, const std::vector<FGate>& fused, const PlanOpts& o, std::vector<PassPlan>& passes,
+                     std::string& err)
+{
+    passes.clear();
+    const int F = (int)fused.size();
+    const bool whole = o.fuse && n <= o.whole_state_max;
+    const int m = whole ? n : std::min(o.tile_qubits, n);
+    const int L = std::min(o.low_qubits, m);
+    std::vector<char> done(F, 0);
+    int remaining = F;
+    const unsigned long long all = (n >= 64) ? ~0ull : ((1ull << n) - 1);
+    while (remaining > 0) {
+        PassPlan pp;
+        int Lp = L;   // low qubits kept in this pass's tile
+        unsigned long long A = (L >= 64) ? ~0ull : ((1ull << L) - 1);
+        if (whole) A = all;
+        // qubits of deferred ops: where some deferred op is not diagonal (blocked), and
+        // where all of them are (blocked_d).  A later op may run ahead of the deferred
+        // ones when it touches no blocked qubit and is itself diagonal on every
+        // blocked_d qubit it touches: it then commutes with each of them.
+        unsigned long long blocked = 0, blocked_d = 0;
+        auto defer = [&](unsigned long long gm, unsigned long long gd) {
+            blocked |= gm & ~gd;
+            blocked_d |= gm & gd;
+            blocked_d &= ~blocked;
+        };
+        double budget = o.pass_budget;
+        for (int i = 0; i < F; ++i) {
+            if (done[i]) continue;
+            const FGate& g = fused[i];
+            unsigned long long gm = 0;
+            for (int j = 0; j < g.k; ++j) gm |= 1ull << g.q[j];
+            const unsigned long long gd = o.commute ? g.dq : 0;
+            if ((gm & blocked) || (gm & ~gd & blocked_d)) { defer(gm, gd); continue; }
+            const double c = op_cost(g, o) + o.sigma;
+            const bool limit_ops = o.max_ops_per_pass > 0 && (int)pp.ops.size() >= o.max_ops_per_pass;
+            const bool fits_budget = whole || o.pass_budget < 0 || c <= budget || pp.ops.empty();
+            unsigned long long nA = (g.kind == OP_DIAG) ? A : (A | gm);
+            if (pp.ops.empty() && __builtin_popcountll(nA) > m) {
+                // a gate wider than the tile's free slots opens a pass with fewer low qubits
+                while (Lp > 0 && __builtin_popcountll(gm | ((1ull << Lp) - 1)) > m) --Lp;
+                A = (1ull << Lp) - 1;
+                nA = A | gm;
+            }
+            const bool fits_tile = __builtin_popcountll(nA) <= m;
+            if (!limit_ops && fits_budget && fits_tile) {
+                A = nA;
+                pp.ops.push_back(i);
+                done[i] = 1;
+                --remaining;
+                budget -= c;
+                pp.cost += c;
+            } else {
+                defer(gm, gd);
+                if ((blocked & all) == all) break;
+            }
+        }
+        // fill the tile up to m qubits with the lowest unused qubits (longer runs)
+        for (int b = 0; b < n && __builtin_popcountll(A) < m; ++b) A |= 1ull << b;
+        for (int b = 0; b < n; ++b)
+            if ((A >> b) & 1) pp.active.push_back(b);
+        pp.low = Lp;
+        if (pp.ops.empty()) { err = "internal: a gate does not fit any tile"; return false; }
+        passes.push_back(pp);
+    }
+
+    return true;
+}
+
 }  // namespace
 
 bool make_plan(int n, int dtype, const std::vector<InGate>& gates, const PlanOpts& o,
@@ -449,62 +738,37 @@ bool make_plan(int n, int dtype, const std::vector<InGate>& gates, const PlanOpt
         }
     }
 
-    // ---- Algorithm 2
-    if (o.fuse == 1) run_fusion(nodes, o);
-    for (const int v : topo_order(nodes))
-        if (!is_identity(nodes[v].g)) P.fused.push_back(nodes[v].g);
-
-    // ---- pass scheduling
-    const int F = (int)P.fused.size();
-    const bool whole = o.fuse && n <= o.whole_state_max;
-    const int m = whole ? n : std::min(o.tile_qubits, n);
-    const int L = std::min(o.low_qubits, m);
-    std::vector<char> done(F, 0);
-    int remaining = F;
-    const unsigned long long all = (n >= 64) ? ~0ull : ((1ull << n) - 1);
-    while (remaining > 0) {
-        PassPlan pp;
-        int Lp = L;   // low qubits kept in this pass's tile
-        unsigned long long A = (L >= 64) ? ~0ull : ((1ull << L) - 1);
-        if (whole) A = all;
-        unsigned long long blocked = 0;
-        double budget = o.pass_budget;
-        for (int i = 0; i < F; ++i) {
-            if (done[i]) continue;
-            const FGate& g = P.fused[i];
-            unsigned long long gm = 0;
-            for (int j = 0; j < g.k; ++j) gm |= 1ull << g.q[j];
-            if (gm & blocked) { blocked |= gm; continue; }
-            const double c = op_cost(g, o) + o.sigma;
-            const bool limit_ops = o.max_ops_per_pass > 0 && (int)pp.ops.size() >= o.max_ops_per_pass;
-            const bool fits_budget = whole || o.pass_budget < 0 || c <= budget || pp.ops.empty();
-            unsigned long long nA = (g.kind == OP_DIAG) ? A : (A | gm);
-            if (pp.ops.empty() && __builtin_popcountll(nA) > m) {
-                // a gate wider than the tile's free slots opens a pass with fewer low qubits
-                while (Lp > 0 && __builtin_popcountll(gm | ((1ull << Lp) - 1)) > m) --Lp;
-                A = (1ull << Lp) - 1;
-                nA = A | gm;
-            }
-            const bool fits_tile = __builtin_popcountll(nA) <= m;
-            if (!limit_ops && fits_budget && fits_tile) {
-                A = nA;
-                pp.ops.push_back(i);
-                done[i] = 1;
-                --remaining;
-                budget -= c;
-                pp.cost += c;
-            } else {
-                blocked |= gm;
-                if ((blocked & all) == all) break;
-            }
+    // ---- Algorithm 2 on the per-qubit DAG; with `commute`, diagonal ops are then also
+    // merged across the commutation-aware DAG, and the whole fusion is run a second time
+    // on that DAG: the plan with fewer passes (then less arithmetic) is kept
+    {
+        if (o.fuse == 1) run_fusion(nodes, o);
+        std::vector<FGate> in;
+        for (const int v : topo_order(nodes)) in.push_back(nodes[v].g);
+        if (o.fuse == 1 && o.commute) in = fuse_commuting(in, n, o, true);
+        for (FGate& g : in)
+            if (!is_identity(g)) P.fused.push_back(std::move(g));
+    }
+    if (!schedule_passes(n, P.fused, o, P.passes, err)) return false;
+    if (o.fuse == 1 && o.commute) {
+        std::vector<FGate> in;
+        in.reserve(gates.size());
+        for (size_t i = 0; i < gates.size(); ++i) in.push_back(canonical(gates[i], (int)i));
+        std::vector<FGate> alt;
+        for (FGate& g : fuse_commuting(in, n, o, false))
+            if (!is_identity(g)) alt.push_back(std::move(g));
+        std::vector<PassPlan> alt_passes;
+        if (!schedule_passes(n, alt, o, alt_passes, err)) return false;
+        auto arith = [&](const std::vector<FGate>& f) {
+            double a = 0;
+            for (const FGate& g : f) a += op_cost(g, o);
+            return a;
+        };
+        if (alt_passes.size() < P.passes.size() ||
+            (alt_passes.size() == P.passes.size() && arith(alt) < arith(P.fused))) {
+            P.fused.swap(alt);
+            P.passes.swap(alt_passes);
         }
-        // fill the tile up to m qubits with the lowest unused qubits (longer runs)
-        for (int b = 0; b < n && __builtin_popcountll(A) < m; ++b) A |= 1ull << b;
-        for (int b = 0; b < n; ++b)
-            if ((A >> b) & 1) pp.active.push_back(b);
-        pp.low = Lp;
-        if (pp.ops.empty()) { err = "internal: a gate does not fit any tile"; return false; }
-        P.passes.push_back(pp);
     }
 
     // ---- device tables

@@ -28,10 +28,13 @@ struct FGate {
     int kind = OP_DENSE;  // OP_DENSE, OP_DIAG or OP_PERM (classified from the matrix)
     int first = 0;        // smallest circuit index among the fused members
     int members = 1;
+    unsigned long long dq = 0;  // physical qubits on which the op is diagonal (it commutes
+                                // with Z on each of them): exactly-zero couplings
 };
 
 struct PlanOpts {
     int fuse = 1;
+    int commute = 1;           // fuse == 1 only: commutation-aware DAG, fusion and scheduling
     int kmax = 5;
     int cost_aware = 1;
     int tile_qubits = 12;
@@ -87,6 +90,14 @@ double op_fma(const FGate& g);
 // ops that run on FP32 MFMA (twice the non-packed VALU rate; FP64 MFMA has the FP64 VALU
 // rate, so complex128 costs are unchanged).
 double op_cost(const FGate& g, const PlanOpts& o);
+
+// Physical qubits on which a fused gate is diagonal: target q[j] counts when every entry
+// coupling rows and columns that differ in local bit j is exactly zero.
+unsigned long long diag_qubit_mask(const FGate& g);
+
+// Two ops commute when on every qubit they share both are diagonal (both are then block
+// diagonal over the shared qubits' basis states, with blocks on disjoint qubits).
+bool ops_commute(const FGate& a, const FGate& b);
 
 // Classifies a dense matrix: OP_DIAG when every off-diagonal entry is exactly zero,
 // OP_PERM when every row and column holds exactly one nonzero, else OP_DENSE.

@@ -659,6 +659,7 @@ qsv_status qsv_server_step(qsv_server s, int* n_running, int* n_pending)
             q->popts.mfma_lds_floats = std::min(q->popts.mfma_lds_floats, kServeOperandFloats);
             if (q->popts.low_qubits >= q->popts.tile_qubits) q->popts.low_qubits = q->popts.tile_qubits - 1;
             q->popts.fuse = r->popts.fuse;
+            q->popts.commute = r->popts.commute;
             if (q->popts.fuse == 0) q->popts.max_ops_per_pass = 1;
             q->gates.swap(r->gates);
             {

@@ -38,7 +38,7 @@ class Gate(ctypes.Structure):
 class PlanOpts(ctypes.Structure):
     _fields_ = [("fuse", ctypes.c_int), ("kmax", ctypes.c_int), ("cost_aware", ctypes.c_int),
                 ("tile_qubits", ctypes.c_int), ("low_qubits", ctypes.c_int),
-                ("pass_budget", ctypes.c_double), ("matrix_cores", ctypes.c_int)]
+                ("pass_budget", ctypes.c_double), ("matrix_cores", ctypes.c_int), ("commute", ctypes.c_int)]
 
 
 class PlanStats(ctypes.Structure):
@@ -230,13 +230,15 @@ class ArrayGateList:
 
 
 def _opts(fuse=True, kmax=0, cost_aware=0, tile_qubits=0, low_qubits=0, pass_budget=0.0,
-          matrix_cores=0) -> PlanOpts:
+          matrix_cores=0, commute=0) -> PlanOpts:
     """fuse: True/1 DAG fusion, False/0 plain (one gate per pass), 2 = no fusion but
-    gates share passes; matrix_cores: complex64 dense ops on >= this many targets use
-    MFMA (0 default, -1 never)."""
+    gates share passes; matrix_cores: dense ops on >= this many targets use MFMA
+    (0 default, -1 never); commute: commutation-aware DAG (0/1 default on, -1 off or
+    False)."""
     o = PlanOpts()
     o.fuse = int(fuse) if not isinstance(fuse, bool) else (1 if fuse else 0)
     o.matrix_cores = matrix_cores
+    o.commute = int(commute) if not isinstance(commute, bool) else (1 if commute else -1)
     o.kmax = kmax
     o.cost_aware = cost_aware
     o.tile_qubits = tile_qubits

@@ -291,3 +291,19 @@ def test_empty_inputs(qsv):
     assert s.sample(np.zeros(0)).size == 0        # no shots
     assert abs(s.norm() - 1) < 1e-7
     s.free()
+
+
+# ------------------------------------------------------------------ commutation-aware plans
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("circuit", ["mix", "h_t_cz"])
+def test_commutation_aware_plans(qsv, dtype, circuit):
+    """Plans whose fusion and passes cross commuting ops (diagonal on every shared
+    qubit) against the oracle, beside the per-qubit DAG and a narrow-tile geometry."""
+    n = 20
+    ops = C.commuting_mix(n, 500, 11) if circuit == "mix" else C.h_t_cz_bricks(n, 16, 3)
+    ref = oracle.simulate(n, ops)
+    for opts in ({}, {"commute": -1}, {"tile_qubits": 8, "low_qubits": 3}, {"kmax": 3}):
+        s = run(qsv, n, dtype, ops, **opts)
+        check_state(s.get(), ref, dtype, str(opts))
+        s.free()

@@ -76,6 +76,8 @@ def test_argument_errors():
         qsv.Plan(16, "c64", C.ghz(16), tile_qubits=14)
     with pytest.raises(qsv.QSVError):
         qsv.Plan(16, "c64", C.ghz(16), kmax=6)
+    with pytest.raises(qsv.QSVError):
+        qsv.Plan(16, "c64", C.ghz(16), commute=2)
 
 
 def test_null_arguments_return_errors():
@@ -290,3 +292,52 @@ def test_device_tables_whole_state_and_workloads(circuit):
         for dt in ("c64", "c128"):
             got = qsv.Plan(n, dt, ops).emulate(psi0)
             assert np.max(np.abs(got - ref)) < 1e-12
+
+
+# ------------------------------------------------------------------ commutation-aware DAG
+
+@pytest.mark.parametrize("seed", range(10))
+@pytest.mark.parametrize("kmax", [2, 3, 5])
+def test_commutation_aware_plan_equals_circuit(seed, kmax):
+    """Fused ops applied in pass order (which may now run commuting ops ahead of earlier
+    ones) reproduce the circuit; the per-qubit DAG gives the same state."""
+    n = 9
+    ops = C.commuting_mix(n, 80, 300 + seed)
+    ref = oracle.simulate(n, ops)
+    for commute in (1, -1):
+        for cost in (1, -1):
+            plan = qsv.Plan(n, "c128", ops, kmax=kmax, cost_aware=cost, commute=commute, tile_qubits=6,
+                            low_qubits=2)
+            assert np.max(np.abs(plan_replay(n, plan) - ref)) < 1e-12, (commute, cost)
+            for targets, m, diag in plan.fused_gates():
+                assert len(targets) <= max(kmax, 3)   # 3-qubit input gates stay as given
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("tq,lq", [(12, 5), (7, 3), (6, 1)])
+def test_commutation_aware_device_tables(seed, tq, lq):
+    rng = np.random.default_rng(400 + seed)
+    n = 14
+    ops = C.commuting_mix(n, 60, 400 + seed) + C.h_t_cz_bricks(n, 3, seed)
+    v = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+    psi0 = np.ascontiguousarray(v / np.linalg.norm(v))
+    ref = oracle.simulate(n, ops, psi=psi0.copy())
+    for dt in ("c64", "c128"):
+        for opts in ({}, {"commute": -1}, {"cost_aware": -1}, {"kmax": 2}):
+            plan = qsv.Plan(n, dt, ops, tile_qubits=tq, low_qubits=lq, **opts)
+            assert np.max(np.abs(plan.emulate(psi0) - ref)) < 1e-12, (dt, opts)
+
+
+def test_commutation_never_adds_passes_and_cuts_them_on_commuting_circuits():
+    n = 24
+    cases = {"brickwork": C.brickwork(n, 10, 3), "qft": C.qft(n),
+             "hea": C.bind(C.hea(n, 4, ring=True), C.hea_params(n, 4, seed=2)),
+             "mix": C.commuting_mix(n, 400, 7), "h_t_cz": C.h_t_cz_bricks(n, 16, 2)}
+    fewer = {}
+    for name, ops in cases.items():
+        for dt in ("c64", "c128"):
+            on = qsv.Plan(n, dt, ops).stats()
+            off = qsv.Plan(n, dt, ops, commute=-1).stats()
+            assert on["passes"] <= off["passes"], (name, dt)
+            fewer[(name, dt)] = off["passes"] - on["passes"]
+    assert fewer[("h_t_cz", "c64")] >= 4 and fewer[("h_t_cz", "c128")] >= 1, fewer
