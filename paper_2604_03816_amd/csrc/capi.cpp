@@ -298,6 +298,8 @@ PassArgs tile_args(int n, int m, int L, unsigned long long need, std::vector<int
 struct ElemGroup {
     PassArgs a;
     TermArgs ta;
+    bool zonly = false;     // every term Z-only: the Z kernel with zt
+    ZTermArgs zt;
     long long ntiles;
     int grid;
     std::vector<int> idx;   // term indices
@@ -313,14 +315,31 @@ bool plan_elements(int n, const std::vector<PTerm>& terms, bool imag, std::vecto
     const unsigned long long lowmask = (L >= 64) ? ~0ull : ((1ull << L) - 1);
     std::vector<std::vector<int>> groups;
     std::vector<unsigned long long> gneed;
+    // Z-only terms get groups of their own (the Z kernel costs one read pass however many
+    // terms it holds); terms with X/Y factors are grouped by their X/Y supports
+    const bool zkernel = m >= kLogThreads && n - m <= kMaxTileIndexBits;
+    size_t nz = 0;
+    if (zkernel) {
+        for (size_t i = 0; i < terms.size(); ++i) {
+            if (terms[i].x) continue;
+            if (nz % kMaxTermsPerLaunch == 0) {
+                groups.push_back({});
+                gneed.push_back(0);
+            }
+            groups.back().push_back((int)i);
+            ++nz;
+        }
+    }
+    const size_t zgroups = groups.size();
     for (size_t i = 0; i < terms.size(); ++i) {
         const unsigned long long x = terms[i].x;
+        if (zkernel && x == 0) continue;
         if (__builtin_popcountll(x | lowmask) > m) {
             err = "Pauli term flips more qubits than one tile holds";
             return false;
         }
         bool placed = false;
-        for (size_t g = 0; g < groups.size() && !placed; ++g) {
+        for (size_t g = zgroups; g < groups.size() && !placed; ++g) {
             const unsigned long long need = gneed[g] | x;
             if (groups[g].size() < (size_t)kMaxTermsPerLaunch && __builtin_popcountll(need | lowmask) <= m) {
                 groups[g].push_back((int)i);
@@ -355,6 +374,29 @@ bool plan_elements(int n, const std::vector<PTerm>& terms, bool imag, std::vecto
             E.ta.zglob[i] = (long long)zg;
             E.ta.ny[i] = p.ny + (imag ? 3 : 0);   // Im z = Re(-i z), and -i = i^3
         }
+        if (g < zgroups) {
+            // signs and lookups of the Z kernel (see ZTermArgs)
+            E.zonly = true;
+            E.zt = ZTermArgs{};
+            E.zt.nterms = E.ta.nterms;
+            const int NS = 1 << (E.a.m - kLogThreads);
+            std::vector<int> outside;   // tile-number bit b <-> outside[b], ascending
+            {
+                unsigned long long A = 0;
+                for (const int q : active) A |= 1ull << q;
+                for (int q = 0; q < n; ++q)
+                    if (!((A >> q) & 1)) outside.push_back(q);
+            }
+            for (int i = 0; i < E.ta.nterms; ++i) {
+                const int q = E.ta.ny[i] & 3;
+                E.zt.zoff[i] = ((q & 1) ? NS : 0) + (E.ta.zloc[i] >> kLogThreads);
+                E.zt.zlo[i] = E.ta.zloc[i] & (kThreads - 1);
+                if (q == 1 || q == 2) E.zt.neg |= 1u << i;
+                if (q & 1) E.zt.zero |= 1u << i;
+                for (size_t b = 0; b < outside.size(); ++b)
+                    if ((E.ta.zglob[i] >> outside[b]) & 1) E.zt.gcol[b] |= 1u << i;
+            }
+        }
         E.ntiles = 1ll << (n - E.a.m);
         E.grid = (int)std::min<long long>(E.ntiles, 1024);
         E.idx = groups[g];
@@ -369,7 +411,9 @@ hipError_t launch_elements(int dtype, const void* sa, const void* sb, const std:
                            double* d_partial, hipStream_t stream)
 {
     for (const ElemGroup& E : G) {
-        const hipError_t e = launch_expval(dtype, sa, sb, E.a, E.ta, E.ntiles, E.grid, d_partial + E.off, stream);
+        const hipError_t e = E.zonly
+            ? launch_expval_z(dtype, sa, sb, E.a, E.zt, E.ntiles, E.grid, d_partial + E.off, stream)
+            : launch_expval(dtype, sa, sb, E.a, E.ta, E.ntiles, E.grid, d_partial + E.off, stream);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -680,8 +680,8 @@ __device__ __forceinline__ void expval_tiles(gptr<C> __restrict__ sa, gptr<C> __
                     const int lb = __ffs(x) - 1;
                     const bool odd = __popc(x & z) & 1;
                     val = 0.0;
-                    for (int p0 = 0; p0 < (NS << (kLogThreads - 1)); p0 += kThreads) {
-                        const int pr = p0 + tid;
+                    // T / 2 pairs: a 2^8 tile has fewer pairs than threads
+                    for (int pr = tid; pr < (NS << (kLogThreads - 1)); pr += kThreads) {
                         const int e = ((pr >> lb) << (lb + 1)) | (pr & ((1 << lb) - 1));
                         const C ap = tla[e ^ x];
                         const C ae = tla[e];
@@ -753,6 +753,110 @@ __global__ __launch_bounds__(kThreads) void k_expval(const C* __restrict__ sa, c
         if (i < t.nterms) {
             NSum v = {acc[i], 0.0};
             const NSum r = block_reduce(v, scratch);
+            if (threadIdx.x == 0) {
+                partial[((long long)blockIdx.x * t.nterms + i) * 2] = r.s;
+                partial[((long long)blockIdx.x * t.nterms + i) * 2 + 1] = r.c;
+            }
+        }
+    }
+}
+
+// Z-only terms: <a|P|b> with P = i^q Z^z sums s(k) i^q conj(a_k) b_k.  As in
+// expval_tiles, a thread's NS elements of a tile are Walsh-transformed over the slice
+// bits, after which a term is one lookup W[zloc >> 8] times signs that are fixed per
+// thread (thread-id bits of z, the phase) or per tile (Z bits outside the tile, a
+// uniform mask built from the tile number's bits).  Each thread reads back only the
+// transform values it wrote, so its LDS slots are private: no barrier, no tile copy.
+template <typename C, int NS, bool TWO>
+__device__ __forceinline__ void expval_z_tiles(gptr<C> __restrict__ sa, gptr<C> __restrict__ sb,
+                                               double* __restrict__ w, const PassArgs& a, const ZTermArgs& t,
+                                               long long ntiles, double (&acc)[kMaxTermsPerLaunch])
+{
+    constexpr int LB = NS >= 8 ? 3 : NS >= 4 ? 2 : NS >= 2 ? 1 : 0;
+    long long hs[LB > 0 ? LB : 1];
+#pragma unroll
+    for (int b = 0; b < LB; ++b) hs[b] = local_stride(a, kLogThreads + b);
+    const int tid = threadIdx.x;
+    const long long tl = local_off_bits(a, tid, 0, kLogThreads);
+    auto soff = [&](int j) {
+        long long so = 0;
+#pragma unroll
+        for (int b = 0; b < LB; ++b)
+            if ((j >> b) & 1) so += hs[b];
+        return so;
+    };
+    unsigned tmask = t.neg;   // per-thread signs: the phase and the thread-id bits of z
+#pragma unroll
+    for (int i = 0; i < kMaxTermsPerLaunch; ++i)
+        if (i < t.nterms) tmask ^= (unsigned)(__popc(tid & t.zlo[i]) & 1) << i;
+    double* wt = w + tid;     // this thread's slots: wt[j << 8], j < NS (real), NS + j (imaginary)
+    for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const long long base = tile_base(a, tile);
+        unsigned gm = 0;      // per-tile signs: Z bits outside the tile
+#pragma unroll
+        for (int b = 0; b < kMaxTileIndexBits; ++b)
+            if ((tile >> b) & 1) gm ^= t.gcol[b];
+        double re[NS], im[NS];
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            const C av = sa[base + tl + soff(j)];
+            const C bv = TWO ? sb[base + tl + soff(j)] : av;
+            re[j] = (double)av.x * (double)bv.x + (double)av.y * (double)bv.y;
+            im[j] = TWO ? (double)av.x * (double)bv.y - (double)av.y * (double)bv.x : 0.0;
+        }
+#pragma unroll
+        for (int h = 1; h < NS; h <<= 1) {
+#pragma unroll
+            for (int j = 0; j < NS; ++j) {
+                if (j & h) continue;
+                const double u = re[j], v = re[j | h];
+                re[j] = u + v;
+                re[j | h] = u - v;
+                if (TWO) {
+                    const double ui = im[j], vi = im[j | h];
+                    im[j] = ui + vi;
+                    im[j | h] = ui - vi;
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            wt[j << kLogThreads] = re[j];
+            if (TWO) wt[(NS + j) << kLogThreads] = im[j];
+        }
+        const unsigned sg = gm ^ tmask;
+#pragma unroll
+        for (int i = 0; i < kMaxTermsPerLaunch; ++i) {
+            if (i < t.nterms && (TWO || !((t.zero >> i) & 1))) {
+                const double v = wt[t.zoff[i] << kLogThreads];
+                acc[i] += ((sg >> i) & 1) ? -v : v;
+            }
+        }
+    }
+}
+
+template <typename C, bool TWO>
+__global__ __launch_bounds__(kThreads) void k_expval_z(const C* __restrict__ sa, const C* __restrict__ sb,
+                                                       const PassArgs a, const ZTermArgs t, long long ntiles,
+                                                       double* __restrict__ partial)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ NSum scratch[kThreads / 64];
+    double* w = reinterpret_cast<double*>(smem);
+    double acc[kMaxTermsPerLaunch];
+#pragma unroll
+    for (int i = 0; i < kMaxTermsPerLaunch; ++i) acc[i] = 0.0;
+    gptr<C> ga = (gptr<C>)const_cast<C*>(sa), gb = (gptr<C>)const_cast<C*>(sb);
+    switch (a.m - kLogThreads) {   // tiles of 2^8 .. 2^11 amplitudes
+    case 0: expval_z_tiles<C, 1, TWO>(ga, gb, w, a, t, ntiles, acc); break;
+    case 1: expval_z_tiles<C, 2, TWO>(ga, gb, w, a, t, ntiles, acc); break;
+    case 2: expval_z_tiles<C, 4, TWO>(ga, gb, w, a, t, ntiles, acc); break;
+    default: expval_z_tiles<C, 8, TWO>(ga, gb, w, a, t, ntiles, acc); break;
+    }
+#pragma unroll
+    for (int i = 0; i < kMaxTermsPerLaunch; ++i) {
+        if (i < t.nterms) {
+            const NSum r = block_reduce(NSum{acc[i], 0.0}, scratch);
             if (threadIdx.x == 0) {
                 partial[((long long)blockIdx.x * t.nterms + i) * 2] = r.s;
                 partial[((long long)blockIdx.x * t.nterms + i) * 2 + 1] = r.c;
@@ -1190,6 +1294,24 @@ hipError_t launch_expval(int dtype, const void* sa, const void* sb, const PassAr
         auto k = two ? k_expval<double2, true> : k_expval<double2, false>;
         hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), expval_lds_bytes(sizeof(double2), a.m, two, anyx), s,
                            (const double2*)sa, (const double2*)sb, a, t, ntiles, partial);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_expval_z(int dtype, const void* sa, const void* sb, const PassArgs& a, const ZTermArgs& t,
+                           long long ntiles, int grid, double* partial, hipStream_t s)
+{
+    const bool two = sb != nullptr && sb != sa;
+    if (a.m < kLogThreads || a.m > kExpvalMaxTileQubits) return hipErrorInvalidValue;
+    const size_t lds = ((two ? 2 : 1) * sizeof(double)) << a.m;
+    if (dtype == 0) {
+        auto k = two ? k_expval_z<float2, true> : k_expval_z<float2, false>;
+        hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds, s, (const float2*)sa, (const float2*)sb, a, t, ntiles,
+                           partial);
+    } else {
+        auto k = two ? k_expval_z<double2, true> : k_expval_z<double2, false>;
+        hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds, s, (const double2*)sa, (const double2*)sb, a, t,
+                           ntiles, partial);
     }
     return hipGetLastError();
 }

@@ -65,6 +65,24 @@ struct TermArgs {
     int ny[kMaxTermsPerLaunch];            // number of Y factors (phase i^ny)
 };
 
+// Work list of the Z-only expectation kernel (every term's X/Y mask is zero).  The
+// host folds each term's phase and global sign into lookups and masks:
+//   zoff[i]   slot of the term in a thread's transform array: (q odd ? NS : 0) + (zloc >> 8)
+//             (q = ny mod 4; odd q selects the imaginary transform)
+//   zlo[i]    the term's Z bits among the thread-id bits (zloc & 255)
+//   neg       bit i: the phase i^q is negative (q = 1 or 2)
+//   zero      bit i: odd q, i.e. the imaginary transform, identically zero when a == b
+//   gcol[b]   bit i: tile-number bit b is a qubit of term i's Z support outside the tile
+constexpr int kMaxTileIndexBits = 24;
+struct ZTermArgs {
+    int nterms;
+    unsigned neg;
+    unsigned zero;
+    int zoff[kMaxTermsPerLaunch];
+    int zlo[kMaxTermsPerLaunch];
+    unsigned gcol[kMaxTileIndexBits];
+};
+
 // A weighted Pauli sum applied to a state (co-state of the adjoint method).
 constexpr int kMaxPauliApply = 64;
 struct PauliSumArgs {
@@ -126,6 +144,9 @@ hipError_t launch_init_zero(int dtype, void* st, long long N, hipStream_t s);
 hipError_t launch_zero(int dtype, void* st, long long N, hipStream_t s);
 int norm_grid(long long N);
 hipError_t launch_norm(int dtype, const void* st, long long N, double* partial, int grid, hipStream_t s);
+// Z-only terms (a.m >= 8): no LDS tile copy and no barriers; grid as for launch_expval.
+hipError_t launch_expval_z(int dtype, const void* sa, const void* sb, const PassArgs& a, const ZTermArgs& t,
+                           long long ntiles, int grid, double* partial, hipStream_t s);
 hipError_t launch_expval(int dtype, const void* sa, const void* sb, const PassArgs& a, const TermArgs& t,
                          long long ntiles, int grid, double* partial, hipStream_t s);
 hipError_t launch_pauli_apply(int dtype, const void* in, void* out, long long N, const PauliSumArgs& p,

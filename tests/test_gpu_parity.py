@@ -217,6 +217,27 @@ def test_norm_probs_expval_random_state(qsv, dtype, n):
     assert abs(tot - math.fsum(want)) <= 1e-12
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [8, 12, 23])
+def test_expval_many_z_terms(qsv, dtype, n):
+    """More Z-only terms than one launch holds (random supports inside and outside the
+    tile, the identity, a Y-free phase), mixed with X/Y terms, against the oracle."""
+    rng = np.random.default_rng(700 + n)
+    psi = rand_state(n, rng)
+    s = qsv.State(n, dtype)
+    s.set(psi)
+    ref = psi if dtype == "c128" else psi.astype(np.complex64).astype(np.complex128)
+    terms = []
+    for _ in range(70):
+        k = int(rng.integers(1, min(n, 6) + 1))
+        terms.append((float(rng.normal()), tuple((int(q), "Z") for q in rng.permutation(n)[:k])))
+    terms += [(1.5, ()), (0.4, ((n - 1, "X"), (0, "Z"))), (-0.8, ((1, "Y"), (n - 2, "Z"), (n // 2, "Z")))]
+    tot, per = s.expval(terms, per_term=True)
+    want = oracle.expval_terms(ref, terms)
+    assert np.max(np.abs(per - want)) <= 1e-13
+    assert abs(tot - math.fsum(want)) <= 1e-12
+
+
 def test_reductions_are_deterministic(qsv):
     n = 22
     s = qsv.State(n, "c64")
