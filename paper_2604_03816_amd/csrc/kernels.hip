@@ -571,14 +571,12 @@ __global__ __launch_bounds__(kThreads) void k_norm(const float4* __restrict__ st
 }
 
 // Pauli matrix elements over tiles: value_t = sum_k Re( i^ny conj(a[k xor x]) b[k] ) *
-// (-1)^popcount(k & zy), i.e. Re <a|P_t|b> (ny may carry an extra 3 to give Im instead).
-// Each term's X/Y support lies inside the tile.  A thread owns local elements
-// e = 256 j + tid (j < NS) of every tile.  The sign of element e splits into a part fixed
-// by the tile and tid and a Walsh function of j, so for all terms without X/Y factors a
-// single Walsh-Hadamard transform over j of the products conj(a_e) b_e (|a_e|^2 when
-// a == b), done in registers once per tile, yields every term as one LDS lookup.  Terms
-// with X/Y factors read their partner amplitude a[e xor x] from an LDS copy of the tile.
-// FP64 per thread; the workgroup partials are combined in a fixed order.
+// (-1)^popcount(k & zy), i.e. Re <a|P_t|b> (ny may carry an extra 3 to give Im instead),
+// for terms with X/Y factors (Z-only terms go to k_expval_z; here they take the generic
+// per-element path).  Each term's X/Y support lies inside the tile.  A thread owns the
+// local elements e = 256 j + tid (j < NS) of every tile and keeps them in registers; the
+// partner amplitudes a[e xor x] come from an LDS copy of the tile of a.  FP64 per thread;
+// the workgroup partials are combined in a fixed order.
 struct TermRow {
     int x, z, q, pad;
     long long g;
@@ -586,16 +584,11 @@ struct TermRow {
 
 template <typename C, int NS, bool TWO>
 __device__ __forceinline__ void expval_tiles(gptr<C> __restrict__ sa, gptr<C> __restrict__ sb,
-                                             unsigned char* __restrict__ smem, const TermRow* __restrict__ rows,
-                                             const PassArgs& a, int nterms, bool anyx, long long ntiles,
+                                             C* __restrict__ tla, const TermRow* __restrict__ rows,
+                                             const PassArgs& a, int nterms, long long ntiles,
                                              double (&acc)[kMaxTermsPerLaunch])
 {
     constexpr int LB = NS >= 32 ? 5 : NS >= 16 ? 4 : NS >= 8 ? 3 : NS >= 4 ? 2 : NS >= 2 ? 1 : 0;
-    constexpr int T = NS << kLogThreads;
-    double* wre = reinterpret_cast<double*>(smem);               // T doubles: transform of Re
-    double* wim = wre + T;                                       // T doubles: transform of Im (TWO)
-    C* tla = reinterpret_cast<C*>(smem + (TWO ? 2 : 1) * T * sizeof(double));   // tile of a (anyx)
-    C* tlb = tla + T;                                            // tile of b (anyx && TWO)
     long long hs[LB > 0 ? LB : 1];
 #pragma unroll
     for (int b = 0; b < LB; ++b) hs[b] = local_stride(a, kLogThreads + b);
@@ -608,6 +601,12 @@ __device__ __forceinline__ void expval_tiles(gptr<C> __restrict__ sa, gptr<C> __
             if ((j >> b) & 1) so += hs[b];
         return so;
     };
+    // real part of i^q w for w = conj(p) e
+    auto phase_re = [](const C& p, const C& e, int q) {
+        const double pr = (double)p.x * (double)e.x + (double)p.y * (double)e.y;
+        const double pi = (double)p.x * (double)e.y - (double)p.y * (double)e.x;
+        return (q == 0) ? pr : (q == 1) ? -pi : (q == 2) ? -pr : pi;
+    };
     for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const long long base = tile_base(a, tile);
         C av[NS], bv[NS];
@@ -617,42 +616,8 @@ __device__ __forceinline__ void expval_tiles(gptr<C> __restrict__ sa, gptr<C> __
 #pragma unroll
             for (int j = 0; j < NS; ++j) bv[j] = sb[base + tl + soff(j)];
         }
-        if (anyx) {
 #pragma unroll
-            for (int j = 0; j < NS; ++j) tla[(j << kLogThreads) + tid] = av[j];
-            if (TWO) {
-#pragma unroll
-                for (int j = 0; j < NS; ++j) tlb[(j << kLogThreads) + tid] = bv[j];
-            }
-        }
-        double re[NS], im[NS];
-#pragma unroll
-        for (int j = 0; j < NS; ++j) {
-            const C be = TWO ? bv[j] : av[j];
-            re[j] = (double)av[j].x * (double)be.x + (double)av[j].y * (double)be.y;
-            im[j] = TWO ? (double)av[j].x * (double)be.y - (double)av[j].y * (double)be.x : 0.0;
-        }
-        // natural-order Walsh-Hadamard transform: w[z] = sum_j (-1)^popcount(j & z) r[j]
-#pragma unroll
-        for (int h = 1; h < NS; h <<= 1) {
-#pragma unroll
-            for (int j = 0; j < NS; ++j) {
-                if (j & h) continue;
-                const double u = re[j], v = re[j | h];
-                re[j] = u + v;
-                re[j | h] = u - v;
-                if (TWO) {
-                    const double ui = im[j], vi = im[j | h];
-                    im[j] = ui + vi;
-                    im[j | h] = ui - vi;
-                }
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < NS; ++j) {
-            wre[(j << kLogThreads) + tid] = re[j];
-            if (TWO) wim[(j << kLogThreads) + tid] = im[j];
-        }
+        for (int j = 0; j < NS; ++j) tla[(j << kLogThreads) + tid] = av[j];
         __syncthreads();
         // the term index stays a compile-time constant so that acc lives in registers;
         // term rows come from LDS so that nothing per term is hoisted out of the tile loop
@@ -663,25 +628,22 @@ __device__ __forceinline__ void expval_tiles(gptr<C> __restrict__ sa, gptr<C> __
                 const int z = __builtin_amdgcn_readfirstlane(rows[i].z);
                 const int q = __builtin_amdgcn_readfirstlane(rows[i].q);
                 const long long g = rows[i].g;
-                const int zhi = z >> kLogThreads;
-                const bool gneg = __popcll(base & g) & 1;                  // bits outside the tile
-                const bool tneg = __popc(tid & z & (kThreads - 1)) & 1;   // bits of the thread id
-                double val;
-                if (x == 0) {
-                    const int w = (zhi << kLogThreads) + tid;
-                    const double r = wre[w], m = TWO ? wim[w] : 0.0;
-                    val = (q == 0) ? r : (q == 1) ? -m : (q == 2) ? -r : m;
-                    if (tneg) val = -val;
-                } else if (!TWO) {
+                const bool gneg = __popcll(base & g) & 1;   // Z bits outside the tile
+                double val = 0.0;
+                if (!TWO && x != 0) {
                     // <a|P|a> over pairs (e, e ^ x), e with x's lowest bit clear: with
                     // w = conj(a[e ^ x]) a[e] the pair adds s(e) i^q (w + (-1)^{|x & z|}
                     // conj(w)), whose real part is 2 Re(i^q w) when |x & z| is even and
                     // 2 Re(i^(q+1) Im(w)) when it is odd: half the elements, one product
                     const int lb = __ffs(x) - 1;
                     const bool odd = __popc(x & z) & 1;
-                    val = 0.0;
-                    // T / 2 pairs: a 2^8 tile has fewer pairs than threads
-                    for (int pr = tid; pr < (NS << (kLogThreads - 1)); pr += kThreads) {
+                    // T / 2 pairs, NP per thread (a 2^8 tile has fewer pairs than threads);
+                    // the unrolled loop issues every partner read before the arithmetic
+                    constexpr int NP = NS >= 2 ? NS / 2 : 1;
+#pragma unroll
+                    for (int p = 0; p < NP; ++p) {
+                        const int pr = p * kThreads + tid;
+                        if (NS == 1 && pr >= (kThreads >> 1)) break;
                         const int e = ((pr >> lb) << (lb + 1)) | (pr & ((1 << lb) - 1));
                         const C ap = tla[e ^ x];
                         const C ae = tla[e];
@@ -696,19 +658,24 @@ __device__ __forceinline__ void expval_tiles(gptr<C> __restrict__ sa, gptr<C> __
                         val += (__popc(e & z) & 1) ? -v : v;
                     }
                     val *= 2.0;
+                } else if (!TWO) {
+                    // x == 0 (Z-only terms normally go to k_expval_z): per element from LDS
+#pragma unroll 1
+                    for (int j = 0; j < NS; ++j) {
+                        const int e = (j << kLogThreads) | tid;
+                        const C ae = tla[e];
+                        const double v = phase_re(ae, ae, q);
+                        val += (__popc(e & z) & 1) ? -v : v;
+                    }
                 } else {
-                    val = 0.0;
-#pragma unroll 4
+                    // per element: the partner from LDS, b[e] from this thread's registers
+#pragma unroll
                     for (int j = 0; j < NS; ++j) {
                         const int e = (j << kLogThreads) | tid;
                         const C ap = tla[e ^ x];
-                        const C be = tlb[e];
-                        const double pr = (double)ap.x * (double)be.x + (double)ap.y * (double)be.y;
-                        const double pi = (double)ap.x * (double)be.y - (double)ap.y * (double)be.x;
-                        const double v = (q == 0) ? pr : (q == 1) ? -pi : (q == 2) ? -pr : pi;
-                        val += (__popc(j & zhi) & 1) ? -v : v;
+                        const double v = phase_re(ap, bv[j], q);
+                        val += (__popc(e & z) & 1) ? -v : v;
                     }
-                    if (tneg) val = -val;
                 }
                 acc[i] += gneg ? -val : val;
             }
@@ -717,10 +684,10 @@ __device__ __forceinline__ void expval_tiles(gptr<C> __restrict__ sa, gptr<C> __
     }
 }
 
-// LDS bytes of one k_expval workgroup for a tile of 2^m amplitudes.
-__host__ __device__ constexpr size_t expval_lds_bytes(size_t elem, int m, bool two, bool anyx)
+// LDS bytes of one k_expval workgroup for a tile of 2^m amplitudes: the tile of a.
+__host__ __device__ constexpr size_t expval_lds_bytes(size_t elem, int m)
 {
-    return ((two ? 2 : 1) * sizeof(double) + (anyx ? (two ? 2 : 1) * elem : 0)) << m;
+    return elem << m;
 }
 
 template <typename C, bool TWO>
@@ -731,8 +698,6 @@ __global__ __launch_bounds__(kThreads) void k_expval(const C* __restrict__ sa, c
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ NSum scratch[kThreads / 64];
     __shared__ TermRow rows[kMaxTermsPerLaunch];
-    bool anyx = false;
-    for (int i = 0; i < t.nterms; ++i) anyx |= t.xloc[i] != 0;
     if (threadIdx.x < t.nterms) {
         const int i = threadIdx.x;
         rows[i] = TermRow{t.xloc[i], t.zloc[i], t.ny[i] & 3, 0, t.zglob[i]};
@@ -742,11 +707,12 @@ __global__ __launch_bounds__(kThreads) void k_expval(const C* __restrict__ sa, c
 #pragma unroll
     for (int i = 0; i < kMaxTermsPerLaunch; ++i) acc[i] = 0.0;
     gptr<C> ga = (gptr<C>)const_cast<C*>(sa), gb = (gptr<C>)const_cast<C*>(sb);
+    C* tla = reinterpret_cast<C*>(smem);
     switch (a.m - kLogThreads) {   // tiles of 2^8 .. 2^11 amplitudes
-    case 0: expval_tiles<C, 1, TWO>(ga, gb, smem, rows, a, t.nterms, anyx, ntiles, acc); break;
-    case 1: expval_tiles<C, 2, TWO>(ga, gb, smem, rows, a, t.nterms, anyx, ntiles, acc); break;
-    case 2: expval_tiles<C, 4, TWO>(ga, gb, smem, rows, a, t.nterms, anyx, ntiles, acc); break;
-    default: expval_tiles<C, 8, TWO>(ga, gb, smem, rows, a, t.nterms, anyx, ntiles, acc); break;
+    case 0: expval_tiles<C, 1, TWO>(ga, gb, tla, rows, a, t.nterms, ntiles, acc); break;
+    case 1: expval_tiles<C, 2, TWO>(ga, gb, tla, rows, a, t.nterms, ntiles, acc); break;
+    case 2: expval_tiles<C, 4, TWO>(ga, gb, tla, rows, a, t.nterms, ntiles, acc); break;
+    default: expval_tiles<C, 8, TWO>(ga, gb, tla, rows, a, t.nterms, ntiles, acc); break;
     }
 #pragma unroll
     for (int i = 0; i < kMaxTermsPerLaunch; ++i) {
@@ -1284,15 +1250,13 @@ hipError_t launch_expval(int dtype, const void* sa, const void* sb, const PassAr
         return hipGetLastError();
     }
     if (a.m > kExpvalMaxTileQubits) return hipErrorInvalidValue;
-    bool anyx = false;
-    for (int i = 0; i < t.nterms; ++i) anyx |= t.xloc[i] != 0;
     if (dtype == 0) {
         auto k = two ? k_expval<float2, true> : k_expval<float2, false>;
-        hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), expval_lds_bytes(sizeof(float2), a.m, two, anyx), s,
+        hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), expval_lds_bytes(sizeof(float2), a.m), s,
                            (const float2*)sa, (const float2*)sb, a, t, ntiles, partial);
     } else {
         auto k = two ? k_expval<double2, true> : k_expval<double2, false>;
-        hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), expval_lds_bytes(sizeof(double2), a.m, two, anyx), s,
+        hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), expval_lds_bytes(sizeof(double2), a.m), s,
                            (const double2*)sa, (const double2*)sb, a, t, ntiles, partial);
     }
     return hipGetLastError();
