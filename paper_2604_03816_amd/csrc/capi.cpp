@@ -307,7 +307,7 @@ struct ElemGroup {
 };
 
 bool plan_elements(int n, const std::vector<PTerm>& terms, bool imag, std::vector<ElemGroup>& G, size_t& doubles,
-                   std::string& err, int dtype)
+                   std::string& err, int dtype, int xgrid = 4096)
 {
     const PlanOpts o = default_opts(dtype);
     const int m = std::min(n, kExpvalMaxTileQubits);
@@ -398,7 +398,10 @@ bool plan_elements(int n, const std::vector<PTerm>& terms, bool imag, std::vecto
             }
         }
         E.ntiles = 1ll << (n - E.a.m);
-        E.grid = (int)std::min<long long>(E.ntiles, 1024);
+        // Z-only groups end with a workgroup reduction per term, so fewer workgroups; the
+        // X/Y kernel is bound by its per-term LDS work and gains from more of them
+        // (measured at 30 qubits; callers that read back many groups ask for fewer)
+        E.grid = (int)std::min<long long>(E.ntiles, E.zonly ? 1024 : xgrid);
         E.idx = groups[g];
         E.off = doubles;
         doubles += (size_t)E.grid * E.ta.nterms * 2;
@@ -1464,7 +1467,7 @@ qsv_status qsv_adjoint_grad(int n, qsv_dtype dtype, const qsv_op* ops, size_t n_
                 gterms[l] = t;
             }
             size_t d = 0;
-            if (!plan_elements(n, gterms, true, Ly.G, d, err, dtype)) return fail(QSV_E_UNSUPPORTED, err);
+            if (!plan_elements(n, gterms, true, Ly.G, d, err, dtype, 1024)) return fail(QSV_E_UNSUPPORTED, err);
             for (ElemGroup& E : Ly.G) E.off += partial_doubles;
             partial_doubles += d;
             layers.push_back(std::move(Ly));
