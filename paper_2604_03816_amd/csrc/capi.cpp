@@ -1054,6 +1054,35 @@ struct DevBuf {
 
 }  // namespace
 
+// Indices of the uniforms in increasing order of value, equal values in index order: an
+// LSD radix sort on the IEEE-754 bit patterns (monotone for non-negative doubles), 16
+// bits per pass, a pass skipped when every key has the same digit.
+static void order_uniforms(const double* u, long long n, std::vector<long long>& order)
+{
+    std::vector<uint64_t> key((size_t)n), k2((size_t)n);
+    std::vector<long long> idx((size_t)n), i2((size_t)n);
+    for (long long i = 0; i < n; ++i) {
+        std::memcpy(&key[i], &u[i], sizeof(double));
+        idx[i] = i;
+    }
+    std::vector<size_t> cnt(65537);
+    for (int pass = 0; pass < 4; ++pass) {
+        const int sh = 16 * pass;
+        std::fill(cnt.begin(), cnt.end(), 0);
+        for (long long i = 0; i < n; ++i) ++cnt[((key[i] >> sh) & 0xFFFF) + 1];
+        if (n > 0 && cnt[((key[0] >> sh) & 0xFFFF) + 1] == (size_t)n) continue;
+        for (int d = 0; d < 65536; ++d) cnt[d + 1] += cnt[d];
+        for (long long i = 0; i < n; ++i) {
+            const size_t p = cnt[(key[i] >> sh) & 0xFFFF]++;
+            k2[p] = key[i];
+            i2[p] = idx[i];
+        }
+        key.swap(k2);
+        idx.swap(i2);
+    }
+    order.swap(idx);
+}
+
 qsv_status qsv_sample(qsv_state s, const int* qubits, int m, const double* uniforms, long long shots,
                       long long* out)
 {
@@ -1110,10 +1139,8 @@ qsv_status qsv_sample(qsv_state s, const int* qubits, int m, const double* unifo
 
     // shots in increasing order of u; each goes to the chunk whose prefix interval holds
     // u * P, with its residual inside that chunk
-    std::vector<long long> order(shots);
-    for (long long i = 0; i < shots; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](long long a, long long b) { return uniforms[a] < uniforms[b]; });
+    std::vector<long long> order;
+    order_uniforms(uniforms, shots, order);
     std::vector<double> res(shots);
     std::vector<SampleChunk> list;
     long long c = 0;
