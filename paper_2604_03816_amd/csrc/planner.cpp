@@ -47,7 +47,7 @@ PlanOpts default_opts(int dtype)
     // arithmetic trade-off that minimises total time).
     if (dtype == 0) {   // complex64: 8-byte amplitudes
         o.tile_qubits = 12;
-        o.low_qubits = 5;
+        o.low_qubits = 4;
         o.whole_state_max = 13;
         o.pass_budget = 160;
         o.sigma = 8;
