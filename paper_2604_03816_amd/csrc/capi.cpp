@@ -1062,7 +1062,8 @@ static void order_uniforms(const double* u, long long n, std::vector<long long>&
     std::vector<uint64_t> key((size_t)n), k2((size_t)n);
     std::vector<long long> idx((size_t)n), i2((size_t)n);
     for (long long i = 0; i < n; ++i) {
-        std::memcpy(&key[i], &u[i], sizeof(double));
+        const double v = u[i] == 0.0 ? 0.0 : u[i];   // -0.0 (accepted as 0) sorts as +0.0
+        std::memcpy(&key[i], &v, sizeof(double));
         idx[i] = i;
     }
     std::vector<size_t> cnt(65537);

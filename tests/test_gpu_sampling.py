@@ -84,6 +84,25 @@ def test_basis_state_many_chunks_and_sorted_order(qsv):
     s.free()
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_repeated_uniforms_zero_and_top(qsv, dtype):
+    """The shot order comes from a sort of the uniforms: repeated values, 0.0, -0.0 and
+    the largest double below 1 in shuffled positions must give the oracle's outcomes."""
+    n = 13
+    s = qsv.State(n, dtype)
+    s.apply(C.brickwork(n, 5, 21))
+    psi = s.get().astype(np.complex128)
+    base = np.random.default_rng(5).random(300)
+    u = np.concatenate([base, base[::-1], base[:50], [0.0, -0.0, 0.0, -0.0], np.full(3, np.nextafter(1.0, 0.0))])
+    np.random.default_rng(6).shuffle(u)
+    got = s.sample(u)
+    assert check_against_oracle(psi, None, u, got) > 0.999
+    assert np.all(got[u == 0.0] == got[np.flatnonzero(u == 0.0)[0]])
+    marg = [12, 0, 7]
+    assert check_against_oracle(psi, marg, u, s.sample(u, marg)) > 0.999
+    s.free()
+
+
 def test_frequencies_match_probabilities(qsv):
     n = 12
     s = qsv.State(n, "c64")
