@@ -487,7 +487,9 @@ qsv_status pauli_sum_apply(qsv_state s, const void* src, void* dst, const std::v
 // Enqueues every pass of a host plan on the state's stream, its tables copied into the
 // state's arena: one asynchronous copy, no allocation once the arena is large enough,
 // no wait for the device (only for the previous copy out of the staging block).
-qsv_status enqueue_plan(qsv_state s, const HostPlan& hp)
+// Uploads the plan's tables into s's arena and enqueues its passes on s's stream; with
+// s2 (same shape and stream) every pass covers both states in one launch.
+qsv_status enqueue_plan(qsv_state s, const HostPlan& hp, qsv_state s2 = nullptr)
 {
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
     const size_t eb = elem_bytes(hp.dtype);
@@ -534,7 +536,8 @@ qsv_status enqueue_plan(qsv_state s, const HostPlan& hp)
     unsigned char* d = s->d_tab;
     for (size_t i = 0; i < hp.passes.size(); ++i)
         QSV_HIP(launch_pass(s->dtype, s->buf, hp.pargs[i], hp.pgrid[i], (const DevOp*)(d + o_ops), d + o_pool,
-                            (const int*)(d + o_ipool), (const float*)(d + o_apool), s->stream));
+                            (const int*)(d + o_ipool), (const float*)(d + o_apool), s->stream,
+                            s2 ? s2->buf : nullptr));
     return QSV_OK;
 }
 
@@ -1543,8 +1546,12 @@ qsv_status qsv_adjoint_grad(int n, qsv_dtype dtype, const qsv_op* ops, size_t n_
                     st = fail(QSV_E_ARG, err);
                     break;
                 }
-                if ((st = enqueue_plan(phi, hp)) != QSV_OK) break;
-                if ((st = enqueue_plan(lam, hp)) != QSV_OK) break;
+                if (phi->stream == lam->stream) {   // one launch per pass for both vectors
+                    if ((st = enqueue_plan(phi, hp, lam)) != QSV_OK) break;
+                } else {
+                    if ((st = enqueue_plan(phi, hp)) != QSV_OK) break;
+                    if ((st = enqueue_plan(lam, hp)) != QSV_OK) break;
+                }
                 pending.clear();
             }
             const hipError_t he = launch_elements(dtype, lam->buf, phi->buf, Ly.G, lam->d_work, lam->stream);

@@ -419,19 +419,25 @@ __device__ __forceinline__ void run_tile(gptr<C> __restrict__ st, C* __restrict_
 }
 
 template <typename C>
-__global__ __launch_bounds__(kThreads) void k_pass(C* __restrict__ st, const PassArgs a, long long ntiles,
+__global__ __launch_bounds__(kThreads) void k_pass(C* __restrict__ st, C* __restrict__ st2, const PassArgs a,
+                                                   long long ntiles,
                                                    const DevOp* __restrict__ ops,
                                                    const C* __restrict__ pool,
                                                    const int* __restrict__ ipool,
                                                    const float* __restrict__ apool)
 {
+    // st2 != nullptr: the same pass on a second state of the same shape (tiles ntiles ..
+    // 2 ntiles - 1 of the work list), e.g. the adjoint's two vectors
     extern __shared__ __align__(16) unsigned char smem[];
     C* lds = reinterpret_cast<C*>(smem);
     float* alds = reinterpret_cast<float*>(smem + (sizeof(C) << a.m));
     stage_operands(alds, (cptr<float>)apool, a);
     __syncthreads();
-    for (long long t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        run_tile<C>((gptr<C>)st, lds, a, t, (cptr<DevOp>)ops, (cptr<C>)pool, (cptr<int>)ipool, alds);
+    const long long total = st2 ? 2 * ntiles : ntiles;
+    for (long long t = blockIdx.x; t < total; t += gridDim.x) {
+        const bool second = t >= ntiles;
+        run_tile<C>((gptr<C>)(second ? st2 : st), lds, a, second ? t - ntiles : t, (cptr<DevOp>)ops, (cptr<C>)pool,
+                    (cptr<int>)ipool, alds);
         __syncthreads();
     }
 }
@@ -1156,8 +1162,8 @@ static int device_cus()
 // Workgroups stride over the tiles (the hardware keeps as many resident as registers and
 // LDS allow; a finished workgroup's slot is refilled at once).
 template <typename R>
-hipError_t launch_pass_t(void* st, const PassArgs& a, long long ntiles, const DevOp* ops, const void* pool,
-                         const int* ipool, const float* apool, hipStream_t s)
+hipError_t launch_pass_t(void* st, void* st2, const PassArgs& a, long long ntiles, const DevOp* ops,
+                         const void* pool, const int* ipool, const float* apool, hipStream_t s)
 {
     using C = typename CT<R>::T;
     static bool attr_set = false;
@@ -1171,8 +1177,8 @@ hipError_t launch_pass_t(void* st, const PassArgs& a, long long ntiles, const De
     // at most 64 workgroups per CU, each striding over tiles: the operand block is staged
     // once per workgroup rather than once per tile (measured on 2^18-tile passes: 6 %
     // faster for complex64, 10 % for complex128 than one workgroup per tile)
-    const long long grid = std::min<long long>(ntiles, 64ll * device_cus());
-    hipLaunchKernelGGL(k_pass<C>, dim3((unsigned)grid), dim3(kThreads), lds, s, (C*)st, a, ntiles, ops,
+    const long long grid = std::min<long long>(st2 ? 2 * ntiles : ntiles, 64ll * device_cus());
+    hipLaunchKernelGGL(k_pass<C>, dim3((unsigned)grid), dim3(kThreads), lds, s, (C*)st, (C*)st2, a, ntiles, ops,
                        (const C*)pool, ipool, apool);
     return hipGetLastError();
 }
@@ -1206,10 +1212,10 @@ hipError_t launch_batch_pass(int dtype, const BatchItem* items, const int* count
 }
 
 hipError_t launch_pass(int dtype, void* st, const PassArgs& a, long long ntiles, const DevOp* ops,
-                       const void* pool, const int* ipool, const float* apool, hipStream_t s)
+                       const void* pool, const int* ipool, const float* apool, hipStream_t s, void* st2)
 {
-    return dtype == 0 ? launch_pass_t<float>(st, a, ntiles, ops, pool, ipool, apool, s)
-                      : launch_pass_t<double>(st, a, ntiles, ops, pool, ipool, apool, s);
+    return dtype == 0 ? launch_pass_t<float>(st, st2, a, ntiles, ops, pool, ipool, apool, s)
+                      : launch_pass_t<double>(st, st2, a, ntiles, ops, pool, ipool, apool, s);
 }
 
 static hipError_t launch_fill16(void* st, long long bytes, uint4 first, uint4 rest, hipStream_t s)
