@@ -1505,6 +1505,15 @@ qsv_status qsv_adjoint_grad(int n, qsv_dtype dtype, const qsv_op* ops, size_t n_
         }
     }
 
+    // the energy's matrix elements <phi|P_t|phi>: their partials follow the layers'
+    std::vector<ElemGroup> Ge;
+    {
+        size_t d = 0;
+        if (!plan_elements(n, hterms, false, Ge, d, err, dtype, 1024)) return fail(QSV_E_UNSUPPORTED, err);
+        for (ElemGroup& E : Ge) E.off += partial_doubles;
+        partial_doubles += d;
+    }
+
     qsv_state phi = nullptr, lam = nullptr;
     qsv_status st = qsv_alloc(n, dtype, nullptr, 0, stream, &phi);
     if (st != QSV_OK) return st;
@@ -1517,22 +1526,34 @@ qsv_status qsv_adjoint_grad(int n, qsv_dtype dtype, const qsv_op* ops, size_t n_
     const size_t pbytes = std::max<size_t>(partial_doubles, 1) * sizeof(double);
     if ((st = ensure_work(lam, pbytes)) == QSV_OK) st = ensure_hwork(lam, pbytes);
     std::vector<double> gv;
+    // the forward circuit's plan for vector b; the next vector's is built on the host
+    // while the device runs the current one
+    auto plan_forward = [&](int b, HostPlan& hp) -> qsv_status {
+        const double* th = params + (size_t)b * P;
+        std::vector<InGate> fwd;
+        fwd.reserve(n_ops);
+        for (size_t i = 0; i < n_ops; ++i) fwd.push_back(op_gate(i, th, false));
+        if (fwd.empty()) return QSV_OK;
+        if (!make_plan(n, dtype, fwd, default_opts(dtype), hp, err)) return fail(QSV_E_ARG, err);
+        return QSV_OK;
+    };
+    HostPlan fwd_cur, fwd_next;
+    if (st == QSV_OK) st = plan_forward(0, fwd_cur);
     for (int b = 0; b < B && st == QSV_OK; ++b) {
         const double* th = params + (size_t)b * P;
         double* gb = grad + (size_t)b * P;
         for (int j = 0; j < P; ++j) gb[j] = 0.0;
         // forward: phi = U(theta)|0>
-        std::vector<InGate> fwd;
-        fwd.reserve(n_ops);
-        for (size_t i = 0; i < n_ops; ++i) fwd.push_back(op_gate(i, th, false));
         if ((st = qsv_reset(phi)) != QSV_OK) break;
-        if ((st = apply_gates(phi, fwd)) != QSV_OK) break;
-        // energy and co-state lambda = H phi
-        std::vector<double> hv;
-        if ((st = expval_core(phi, hterms, hv)) != QSV_OK) break;
-        NS e;
-        for (size_t t = 0; t < hterms.size(); ++t) e.add(hterms[t].coeff * hv[t]);
-        energy[b] = e.value();
+        if (n_ops && (st = enqueue_plan(phi, fwd_cur)) != QSV_OK) break;
+        // energy (partials read back with the gradients) and co-state lambda = H phi
+        {
+            const hipError_t he = launch_elements(dtype, phi->buf, phi->buf, Ge, lam->d_work, lam->stream);
+            if (he != hipSuccess) {
+                st = fail(QSV_E_DEVICE, std::string("adjoint: ") + hipGetErrorString(he));
+                break;
+            }
+        }
         if ((st = pauli_sum_apply(lam, phi->buf, lam->buf, hterms)) != QSV_OK) break;
         // reverse sweep, asynchronous: uncompute (fixed gates and the previous layer,
         // one plan applied to both states), then the layer's Im <lambda|P_j|phi>
@@ -1562,8 +1583,12 @@ qsv_status qsv_adjoint_grad(int n, qsv_dtype dtype, const qsv_op* ops, size_t n_
             for (const long long k : Ly.ops) pending.push_back(op_gate((size_t)k, th, true));
         }
         if (st != QSV_OK) break;
-        if (hipMemcpyAsync(lam->h_work, lam->d_work, pbytes, hipMemcpyDeviceToHost, lam->stream) != hipSuccess ||
-            hipStreamSynchronize(lam->stream) != hipSuccess) {
+        if (hipMemcpyAsync(lam->h_work, lam->d_work, pbytes, hipMemcpyDeviceToHost, lam->stream) != hipSuccess) {
+            st = fail(QSV_E_DEVICE, "adjoint: partials read-back failed");
+            break;
+        }
+        if (b + 1 < B && (st = plan_forward(b + 1, fwd_next)) != QSV_OK) break;
+        if (hipStreamSynchronize(lam->stream) != hipSuccess) {
             st = fail(QSV_E_DEVICE, "adjoint: partials read-back failed");
             break;
         }
@@ -1571,6 +1596,11 @@ qsv_status qsv_adjoint_grad(int n, qsv_dtype dtype, const qsv_op* ops, size_t n_
             combine_elements(Ly.G, lam->h_work, Ly.ops.size(), gv);
             for (size_t l = 0; l < Ly.ops.size(); ++l) gb[ops[Ly.ops[l]].param] += gv[l];
         }
+        combine_elements(Ge, lam->h_work, hterms.size(), gv);
+        NS e;
+        for (size_t t = 0; t < hterms.size(); ++t) e.add(hterms[t].coeff * gv[t]);
+        energy[b] = e.value();
+        std::swap(fwd_cur, fwd_next);
     }
     qsv_free(phi);
     qsv_free(lam);
