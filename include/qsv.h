@@ -176,6 +176,14 @@ qsv_status qsv_plan_apply(qsv_state s, qsv_plan p);
 /* Enqueues only passes [first, first+count) of the plan (for timing single passes). */
 qsv_status qsv_plan_apply_range(qsv_state s, qsv_plan p, size_t first, size_t count);
 
+/* Sets the state to passes [0, count) of the plan applied to |0...0> (Eq. 1), whatever
+ * the buffer held: the first pass builds the |0...0> tiles on chip instead of reading
+ * them, so the initialisation costs no HBM traffic of its own.  count = the plan's pass
+ * count applies the whole circuit; count == 0 only resets the state.  QSV_E_ARG when
+ * count exceeds the pass count or the plan does not match the state.  Asynchronous,
+ * like qsv_plan_apply. */
+qsv_status qsv_plan_apply_zero(qsv_state s, qsv_plan p, size_t count);
+
 /* One call = plan + apply + release; synchronises the stream before returning.
  * stats may be NULL. */
 qsv_status qsv_apply_fused(qsv_state s, const qsv_gate* gates, size_t n_gates,

@@ -488,9 +488,15 @@ qsv_status pauli_sum_apply(qsv_state s, const void* src, void* dst, const std::v
 // state's arena: one asynchronous copy, no allocation once the arena is large enough,
 // no wait for the device (only for the previous copy out of the staging block).
 // Uploads the plan's tables into s's arena and enqueues its passes on s's stream; with
-// s2 (same shape and stream) every pass covers both states in one launch.
-qsv_status enqueue_plan(qsv_state s, const HostPlan& hp, qsv_state s2 = nullptr)
+// s2 (same shape and stream) every pass covers both states in one launch; from_zero: the
+// input is |0...0> (the first pass builds it on chip; no passes: s is reset).
+qsv_status enqueue_plan(qsv_state s, const HostPlan& hp, qsv_state s2 = nullptr, bool from_zero = false)
 {
+    if (from_zero && hp.passes.empty()) {
+        QSV_HIP(launch_init_zero(s->dtype, s->buf, 1ll << s->n, s->stream));
+        if (s2) QSV_HIP(launch_init_zero(s2->dtype, s2->buf, 1ll << s2->n, s2->stream));
+        return QSV_OK;
+    }
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
     const size_t eb = elem_bytes(hp.dtype);
     const size_t o_ops = 0;
@@ -537,7 +543,7 @@ qsv_status enqueue_plan(qsv_state s, const HostPlan& hp, qsv_state s2 = nullptr)
     for (size_t i = 0; i < hp.passes.size(); ++i)
         QSV_HIP(launch_pass(s->dtype, s->buf, hp.pargs[i], hp.pgrid[i], (const DevOp*)(d + o_ops), d + o_pool,
                             (const int*)(d + o_ipool), (const float*)(d + o_apool), s->stream,
-                            s2 ? s2->buf : nullptr));
+                            s2 ? s2->buf : nullptr, from_zero && i == 0));
     return QSV_OK;
 }
 
@@ -895,6 +901,29 @@ qsv_status qsv_plan_apply_range(qsv_state s, qsv_plan p, size_t first, size_t co
         const PassArgs& a = p->hp.pargs[i];
         QSV_HIP(launch_pass(s->dtype, s->buf, a, p->hp.pgrid[i], p->d_ops, p->d_pool, p->d_ipool, p->d_apool,
                             s->stream));
+    }
+    return QSV_OK;
+}
+
+qsv_status qsv_plan_apply_zero(qsv_state s, qsv_plan p, size_t count)
+{
+    qsv_status st = check_state(s);
+    if (st != QSV_OK) return st;
+    if (!p) return fail(QSV_E_ARG, "null plan");
+    if (p->hp.n != s->n || p->hp.dtype != s->dtype) return fail(QSV_E_ARG, "plan does not match the state's n / dtype");
+    const size_t np = p->hp.passes.size();
+    if (count > np) return fail(QSV_E_ARG, "pass count out of bounds");
+    DeviceGuard g(s->device);
+    if (count == 0) {
+        QSV_HIP(launch_init_zero(s->dtype, s->buf, 1ll << s->n, s->stream));
+        return QSV_OK;
+    }
+    st = upload_plan(p, s->device);
+    if (st != QSV_OK) return st;
+    for (size_t i = 0; i < count; ++i) {
+        const PassArgs& a = p->hp.pargs[i];
+        QSV_HIP(launch_pass(s->dtype, s->buf, a, p->hp.pgrid[i], p->d_ops, p->d_pool, p->d_ipool, p->d_apool,
+                            s->stream, nullptr, i == 0));
     }
     return QSV_OK;
 }
@@ -1544,8 +1573,11 @@ qsv_status qsv_adjoint_grad(int n, qsv_dtype dtype, const qsv_op* ops, size_t n_
         double* gb = grad + (size_t)b * P;
         for (int j = 0; j < P; ++j) gb[j] = 0.0;
         // forward: phi = U(theta)|0>
-        if ((st = qsv_reset(phi)) != QSV_OK) break;
-        if (n_ops && (st = enqueue_plan(phi, fwd_cur)) != QSV_OK) break;
+        if (n_ops) {
+            if ((st = enqueue_plan(phi, fwd_cur, nullptr, true)) != QSV_OK) break;
+        } else if ((st = qsv_reset(phi)) != QSV_OK) {
+            break;
+        }
         // energy (partials read back with the gradients) and co-state lambda = H phi
         {
             const hipError_t he = launch_elements(dtype, phi->buf, phi->buf, Ge, lam->d_work, lam->stream);

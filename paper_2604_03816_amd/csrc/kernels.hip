@@ -409,10 +409,21 @@ __device__ __forceinline__ void stage_operands(float* __restrict__ alds, cptr<fl
 template <typename C>
 __device__ __forceinline__ void run_tile(gptr<C> __restrict__ st, C* __restrict__ lds, const PassArgs& a,
                                          long long tile, cptr<DevOp> __restrict__ ops, cptr<C> __restrict__ pool,
-                                         cptr<int> __restrict__ ipool, const float* __restrict__ alds)
+                                         cptr<int> __restrict__ ipool, const float* __restrict__ alds,
+                                         bool from_zero = false)
 {
     const long long base = tile_base(a, tile);
-    move_tile<C, true>(st, lds, a, base);
+    if (from_zero) {
+        // the tile of |0...0> (Eq. 1): built on chip instead of read from HBM
+        for (int e = threadIdx.x; e < (1 << a.m); e += kThreads) {
+            C z;
+            z.x = (base == 0 && e == 0) ? 1 : 0;
+            z.y = 0;
+            lds[e] = z;
+        }
+    } else {
+        move_tile<C, true>(st, lds, a, base);
+    }
     __syncthreads();
     apply_ops<C>(lds, 1 << a.m, ops, a.op_begin, a.op_count, pool, ipool, alds, base);
     move_tile<C, false>(st, lds, a, base);
@@ -420,14 +431,16 @@ __device__ __forceinline__ void run_tile(gptr<C> __restrict__ st, C* __restrict_
 
 template <typename C>
 __global__ __launch_bounds__(kThreads) void k_pass(C* __restrict__ st, C* __restrict__ st2, const PassArgs a,
-                                                   long long ntiles,
+                                                   long long ntiles, int from_zero,
                                                    const DevOp* __restrict__ ops,
                                                    const C* __restrict__ pool,
                                                    const int* __restrict__ ipool,
                                                    const float* __restrict__ apool)
 {
     // st2 != nullptr: the same pass on a second state of the same shape (tiles ntiles ..
-    // 2 ntiles - 1 of the work list), e.g. the adjoint's two vectors
+    // 2 ntiles - 1 of the work list), e.g. the adjoint's two vectors.  from_zero: the
+    // input is |0...0>, whatever the state buffers hold (a circuit's first pass, with the
+    // initialisation folded in)
     extern __shared__ __align__(16) unsigned char smem[];
     C* lds = reinterpret_cast<C*>(smem);
     float* alds = reinterpret_cast<float*>(smem + (sizeof(C) << a.m));
@@ -437,7 +450,7 @@ __global__ __launch_bounds__(kThreads) void k_pass(C* __restrict__ st, C* __rest
     for (long long t = blockIdx.x; t < total; t += gridDim.x) {
         const bool second = t >= ntiles;
         run_tile<C>((gptr<C>)(second ? st2 : st), lds, a, second ? t - ntiles : t, (cptr<DevOp>)ops, (cptr<C>)pool,
-                    (cptr<int>)ipool, alds);
+                    (cptr<int>)ipool, alds, from_zero != 0);
         __syncthreads();
     }
 }
@@ -1163,7 +1176,7 @@ static int device_cus()
 // LDS allow; a finished workgroup's slot is refilled at once).
 template <typename R>
 hipError_t launch_pass_t(void* st, void* st2, const PassArgs& a, long long ntiles, const DevOp* ops,
-                         const void* pool, const int* ipool, const float* apool, hipStream_t s)
+                         const void* pool, const int* ipool, const float* apool, hipStream_t s, bool from_zero)
 {
     using C = typename CT<R>::T;
     static bool attr_set = false;
@@ -1178,8 +1191,8 @@ hipError_t launch_pass_t(void* st, void* st2, const PassArgs& a, long long ntile
     // once per workgroup rather than once per tile (measured on 2^18-tile passes: 6 %
     // faster for complex64, 10 % for complex128 than one workgroup per tile)
     const long long grid = std::min<long long>(st2 ? 2 * ntiles : ntiles, 64ll * device_cus());
-    hipLaunchKernelGGL(k_pass<C>, dim3((unsigned)grid), dim3(kThreads), lds, s, (C*)st, (C*)st2, a, ntiles, ops,
-                       (const C*)pool, ipool, apool);
+    hipLaunchKernelGGL(k_pass<C>, dim3((unsigned)grid), dim3(kThreads), lds, s, (C*)st, (C*)st2, a, ntiles,
+                       from_zero ? 1 : 0, ops, (const C*)pool, ipool, apool);
     return hipGetLastError();
 }
 
@@ -1212,10 +1225,11 @@ hipError_t launch_batch_pass(int dtype, const BatchItem* items, const int* count
 }
 
 hipError_t launch_pass(int dtype, void* st, const PassArgs& a, long long ntiles, const DevOp* ops,
-                       const void* pool, const int* ipool, const float* apool, hipStream_t s, void* st2)
+                       const void* pool, const int* ipool, const float* apool, hipStream_t s, void* st2,
+                       bool from_zero)
 {
-    return dtype == 0 ? launch_pass_t<float>(st, st2, a, ntiles, ops, pool, ipool, apool, s)
-                      : launch_pass_t<double>(st, st2, a, ntiles, ops, pool, ipool, apool, s);
+    return dtype == 0 ? launch_pass_t<float>(st, st2, a, ntiles, ops, pool, ipool, apool, s, from_zero)
+                      : launch_pass_t<double>(st, st2, a, ntiles, ops, pool, ipool, apool, s, from_zero);
 }
 
 static hipError_t launch_fill16(void* st, long long bytes, uint4 first, uint4 rest, hipStream_t s)

@@ -69,7 +69,8 @@ class COp(ctypes.Structure):
 EXPORTS = [
     "qsv_last_error", "qsv_version", "qsv_alloc", "qsv_free", "qsv_reset", "qsv_info", "qsv_get_state",
     "qsv_set_state", "qsv_gate_matrix", "qsv_plan_create", "qsv_plan_free", "qsv_plan_get_stats",
-    "qsv_plan_fused_gate", "qsv_plan_pass_info", "qsv_plan_pass_ops", "qsv_plan_emulate", "qsv_plan_apply", "qsv_plan_apply_range",
+    "qsv_plan_fused_gate", "qsv_plan_pass_info", "qsv_plan_pass_ops", "qsv_plan_emulate", "qsv_plan_apply",
+    "qsv_plan_apply_range", "qsv_plan_apply_zero",
     "qsv_apply_fused", "qsv_sync", "qsv_norm", "qsv_expval_pauli", "qsv_probs", "qsv_sample", "qsv_adjoint_grad",
     "qsv_dm_apply", "qsv_dm_probs", "qsv_dm_expval_pauli", "qsv_precision_select",
     "qsv_server_create", "qsv_server_free", "qsv_server_submit", "qsv_server_step", "qsv_server_results",
@@ -106,6 +107,7 @@ def lib():
     L.qsv_plan_emulate.argtypes = [vp, dp]
     L.qsv_plan_apply.argtypes = [vp, vp]
     L.qsv_plan_apply_range.argtypes = [vp, vp, sz, sz]
+    L.qsv_plan_apply_zero.argtypes = [vp, vp, sz]
     L.qsv_apply_fused.argtypes = [vp, ctypes.POINTER(Gate), sz, ctypes.POINTER(PlanOpts), ctypes.POINTER(PlanStats)]
     L.qsv_sync.argtypes = [vp]
     L.qsv_norm.argtypes = [vp, dp]
@@ -354,6 +356,11 @@ class State:
         o = _opts(**opts)
         check(lib().qsv_apply_fused(self.h, gl.arr, gl.n, ctypes.byref(o), ctypes.byref(st)))
         return st.as_dict()
+
+    def apply_plan_zero(self, plan: Plan, count: int = None) -> None:
+        """The first ``count`` passes (default all) applied to |0...0>, the initial state
+        built inside the first pass (no separate reset)."""
+        check(lib().qsv_plan_apply_zero(self.h, plan.h, plan.stats()["passes"] if count is None else count))
 
     def apply_plan(self, plan: Plan, first: int = None, count: int = None) -> None:
         if first is None:

@@ -328,3 +328,35 @@ def test_commutation_aware_plans(qsv, dtype, circuit):
         s = run(qsv, n, dtype, ops, **opts)
         check_state(s.get(), ref, dtype, str(opts))
         s.free()
+
+
+# ------------------------------------------------------------------ |0...0> built inside the first pass
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [10, 16, 22])
+def test_apply_zero_matches_reset_then_apply(qsv, dtype, n):
+    """qsv_plan_apply_zero ignores the buffer's contents: from a random state it gives
+    the circuit applied to |0...0>, for the whole plan, a prefix of it and no pass."""
+    rng = np.random.default_rng(60 + n)
+    ops = C.brickwork(n, 6, 7) + C.ghz(n)
+    ref = oracle.simulate(n, ops)
+    plan = qsv.Plan(n, dtype, ops, tile_qubits=min(n, 8) if n > 12 else 0)
+    s = qsv.State(n, dtype)
+    s.set(rand_state(n, rng))
+    s.apply_plan_zero(plan)
+    check_state(s.get(), ref, dtype)
+    npass = plan.stats()["passes"]
+    if npass > 1:
+        s.set(rand_state(n, rng))
+        s.apply_plan_zero(plan, 1)
+        s.apply_plan(plan, 1, npass - 1)
+        check_state(s.get(), ref, dtype, "prefix then the rest")
+    s.set(rand_state(n, rng))
+    s.apply_plan_zero(plan, 0)
+    z = np.zeros(1 << n, complex)
+    z[0] = 1
+    check_state(s.get(), z, dtype, "count 0")
+    with pytest.raises(qsv.QSVError):
+        s.apply_plan_zero(plan, npass + 1)
+    s.free()
+    plan.free()
