@@ -3,7 +3,7 @@
 // State layout: 2^n interleaved complex numbers (float2 for complex64, double2 for
 // complex128), qubit t = bit t of the index (Eq. 2 / Eq. 3).
 //
-// Apply pass (k_pass): one workgroup per tile.  A tile is 2^m amplitudes whose
+// Apply pass (k_pass): each workgroup takes tiles in turn.  A tile is 2^m amplitudes whose
 // indices differ only in the pass's m tile qubits: the L lowest qubits (so each tile
 // row is a contiguous run of 2^L amplitudes in HBM) plus m - L higher qubits (rows
 // strided by 2^q).  The workgroup streams its tile from HBM into LDS, applies every
@@ -397,7 +397,7 @@ __device__ __forceinline__ void apply_ops(C* __restrict__ lds, int T, cptr<DevOp
     }
 }
 
-// The pass's MFMA operand block, global -> LDS (once per kernel, or per work item in
+// The pass's MFMA operand block, global -> LDS (once per workgroup, or per work item in
 // batched launches).
 __device__ __forceinline__ void stage_operands(float* __restrict__ alds, cptr<float> __restrict__ apool,
                                                const PassArgs& a)

@@ -53,8 +53,8 @@ struct PassArgs {
 // Work list for the expectation kernel: up to kMaxTermsPerLaunch Pauli strings whose
 // X/Y supports all lie inside the tile.
 constexpr int kMaxTermsPerLaunch = 32;
-// Tile qubits of the Pauli matrix-element kernel (2^11 amplitudes: the per-tile Walsh
-// transforms and the tile copy of two complex128 states fit 64 KiB of LDS).
+// Tile qubits of the Pauli matrix-element kernels (2^11 amplitudes: the tile copy of a
+// complex128 state, or the Z kernel's per-thread transform slots, fit 32 KiB of LDS).
 constexpr int kExpvalMaxTileQubits = 11;
 
 struct TermArgs {
