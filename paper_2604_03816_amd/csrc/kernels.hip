@@ -355,7 +355,10 @@ __device__ __forceinline__ void op_diag(C* __restrict__ lds, int T, const DevOp&
     }
 }
 
-template <typename C>
+// WIDE = false leaves out the register-heavy paths (VALU dense ops on 4 or 5 targets,
+// permutations on 3 or more): the caller launches that variant only for passes without
+// such ops, and its lower register count allows more resident workgroups.
+template <typename C, bool WIDE = true>
 __device__ __forceinline__ void apply_ops(C* __restrict__ lds, int T, cptr<DevOp> __restrict__ ops, int op_begin,
                           int op_count, cptr<C> __restrict__ pool, cptr<int> __restrict__ ipool,
                           const float* __restrict__ alds, long long base)
@@ -376,17 +379,17 @@ __device__ __forceinline__ void apply_ops(C* __restrict__ lds, int T, cptr<DevOp
             case 1: op_dense<C, 1>(lds, T, op, M); break;
             case 2: op_dense<C, 2>(lds, T, op, M); break;
             case 3: op_dense<C, 3>(lds, T, op, M); break;
-            case 4: op_dense<C, 4>(lds, T, op, M); break;
-            default: op_dense<C, 5>(lds, T, op, M); break;
+            case 4: if constexpr (WIDE) op_dense<C, 4>(lds, T, op, M); break;
+            default: if constexpr (WIDE) op_dense<C, 5>(lds, T, op, M); break;
             }
         } else if (op.kind == OP_PERM) {
             cptr<int> S = ipool + op.ioff;
             switch (op.k) {
             case 1: op_perm<C, 1>(lds, T, op, M, S); break;
             case 2: op_perm<C, 2>(lds, T, op, M, S); break;
-            case 3: op_perm<C, 3>(lds, T, op, M, S); break;
-            case 4: op_perm<C, 4>(lds, T, op, M, S); break;
-            default: op_perm<C, 5>(lds, T, op, M, S); break;
+            case 3: if constexpr (WIDE) op_perm<C, 3>(lds, T, op, M, S); break;
+            case 4: if constexpr (WIDE) op_perm<C, 4>(lds, T, op, M, S); break;
+            default: if constexpr (WIDE) op_perm<C, 5>(lds, T, op, M, S); break;
             }
         } else if (op.aoff >= 0) {
             op_diag<C>(lds, T, op, reinterpret_cast<const C*>(alds + op.aoff), base);
@@ -406,7 +409,7 @@ __device__ __forceinline__ void stage_operands(float* __restrict__ alds, cptr<fl
 }
 
 // One tile of one pass: HBM -> LDS, every op of the pass, LDS -> HBM.
-template <typename C>
+template <typename C, bool WIDE = true>
 __device__ __forceinline__ void run_tile(gptr<C> __restrict__ st, C* __restrict__ lds, const PassArgs& a,
                                          long long tile, cptr<DevOp> __restrict__ ops, cptr<C> __restrict__ pool,
                                          cptr<int> __restrict__ ipool, const float* __restrict__ alds,
@@ -425,7 +428,7 @@ __device__ __forceinline__ void run_tile(gptr<C> __restrict__ st, C* __restrict_
         move_tile<C, true>(st, lds, a, base);
     }
     __syncthreads();
-    apply_ops<C>(lds, 1 << a.m, ops, a.op_begin, a.op_count, pool, ipool, alds, base);
+    apply_ops<C, WIDE>(lds, 1 << a.m, ops, a.op_begin, a.op_count, pool, ipool, alds, base);
     move_tile<C, false>(st, lds, a, base);
 }
 
@@ -459,7 +462,7 @@ __global__ __launch_bounds__(kThreads) void k_pass(C* __restrict__ st, C* __rest
 // each by its own current pass.  Work item w (a tile of one item's pass) is found by
 // binary search over the items' tile prefix sums; the grid is persistent (fixed size,
 // strided over the work list) so the launch can be captured once and replayed.
-template <typename C>
+template <typename C, bool WIDE>
 __global__ __launch_bounds__(kThreads) void k_batch_pass(const BatchItem* __restrict__ items,
                                                          const int* __restrict__ count)
 {
@@ -471,6 +474,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_pass(const BatchItem* __rest
     for (int i = threadIdx.x; i < nitems; i += kThreads) ends[i] = items[i].tile_end;
     __syncthreads();
     const long long total = ends[nitems - 1];
+    int staged = -1;   // item whose operand block LDS holds (consecutive tiles often share one)
     for (long long w = blockIdx.x; w < total; w += gridDim.x) {
         int lo = 0, hi = nitems - 1;
         while (lo < hi) {
@@ -487,12 +491,13 @@ __global__ __launch_bounds__(kThreads) void k_batch_pass(const BatchItem* __rest
         // pointers read from memory carry no address space: state in global memory
         // (global, not flat, loads and stores), plan tables read-only (scalar loads)
         float* alds = reinterpret_cast<float*>(smem + (sizeof(C) << it.a.m));
-        if (it.a.a_len > 0) {
+        if (it.a.a_len > 0 && lo != staged) {
             stage_operands(alds, (cptr<float>)it.apool, it.a);
             __syncthreads();
+            staged = lo;
         }
-        run_tile<C>((gptr<C>)it.state, lds, it.a, tile, (cptr<DevOp>)it.ops, (cptr<C>)it.pool,
-                    (cptr<int>)it.ipool, alds);
+        run_tile<C, WIDE>((gptr<C>)it.state, lds, it.a, tile, (cptr<DevOp>)it.ops, (cptr<C>)it.pool,
+                          (cptr<int>)it.ipool, alds);
         __syncthreads();   // the next work item reuses the LDS tile
     }
 }
@@ -1196,32 +1201,31 @@ hipError_t launch_pass_t(void* st, void* st2, const PassArgs& a, long long ntile
     return hipGetLastError();
 }
 
+template <typename C, bool WIDE>
+static hipError_t launch_batch_pass_t(const BatchItem* items, const int* count, int grid, size_t lds, hipStream_t s)
+{
+    static bool set = false;
+    if (!set) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_batch_pass<C, WIDE>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+        if (e != hipSuccess) return e;
+        set = true;
+    }
+    hipLaunchKernelGGL((k_batch_pass<C, WIDE>), dim3(grid), dim3(kThreads), lds, s, items, count);
+    return hipGetLastError();
+}
+
 hipError_t launch_batch_pass(int dtype, const BatchItem* items, const int* count, int grid, int tile_qubits,
-                             hipStream_t s)
+                             hipStream_t s, bool wide)
 {
     // tile + the per-pass operand block (MFMA matrices, diagonal tables) of either dtype
     const size_t lds = ((dtype == 0 ? sizeof(float2) : sizeof(double2)) << tile_qubits) +
                        sizeof(float) * kServeOperandFloats;
-    if (dtype == 0) {
-        static bool set = false;
-        if (!set) {
-            hipError_t e = hipFuncSetAttribute((const void*)k_batch_pass<float2>,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
-            if (e != hipSuccess) return e;
-            set = true;
-        }
-        hipLaunchKernelGGL(k_batch_pass<float2>, dim3(grid), dim3(kThreads), lds, s, items, count);
-    } else {
-        static bool set = false;
-        if (!set) {
-            hipError_t e = hipFuncSetAttribute((const void*)k_batch_pass<double2>,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
-            if (e != hipSuccess) return e;
-            set = true;
-        }
-        hipLaunchKernelGGL(k_batch_pass<double2>, dim3(grid), dim3(kThreads), lds, s, items, count);
-    }
-    return hipGetLastError();
+    if (dtype == 0)
+        return wide ? launch_batch_pass_t<float2, true>(items, count, grid, lds, s)
+                    : launch_batch_pass_t<float2, false>(items, count, grid, lds, s);
+    return wide ? launch_batch_pass_t<double2, true>(items, count, grid, lds, s)
+                : launch_batch_pass_t<double2, false>(items, count, grid, lds, s);
 }
 
 hipError_t launch_pass(int dtype, void* st, const PassArgs& a, long long ntiles, const DevOp* ops,

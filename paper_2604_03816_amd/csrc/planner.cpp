@@ -877,6 +877,14 @@ bool make_plan(int n, int dtype, const std::vector<InGate>& gates, const PlanOpt
             P.fma_per_amp += op_fma(g);
             P.ops.push_back(d);
         }
+        {
+            bool wide = false;
+            for (int i = a.op_begin; i < a.op_begin + a.op_count; ++i) {
+                const DevOp& d = P.ops[(size_t)i];
+                wide |= (d.kind == OP_DENSE && d.aoff < 0 && d.k >= 4) || (d.kind == OP_PERM && d.k >= 3);
+            }
+            P.pwide.push_back(wide ? 1 : 0);
+        }
         P.pargs.push_back(a);
         P.pgrid.push_back(1ll << (n - a.m));
     }

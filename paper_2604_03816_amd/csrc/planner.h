@@ -67,6 +67,8 @@ struct HostPlan {
     std::vector<DevOp> ops;
     std::vector<PassArgs> pargs;
     std::vector<long long> pgrid;  // tiles per pass
+    std::vector<char> pwide;       // pass has a VALU dense op on >= 4 targets or a permutation on
+                                   // >= 3 (the register-heavy paths of the pass kernels)
     std::vector<cd> pool;
     std::vector<int> ipool;
     std::vector<float> apool;      // MFMA operand blocks, one contiguous block per pass

@@ -278,12 +278,16 @@ hipError_t launch_step(qsv_server s)
 {
     const int P = passes_per_step(s);
     const int grid = s->o.grid > 0 ? s->o.grid : 2048;
+    // work list (wide, dtype, j) at slot (2 wide + dtype) P + j: passes with register-heavy
+    // ops go to the wide kernel variant, the rest to the lighter one
     for (int j = 0; j < P; ++j)
-        for (int dt = 0; dt < 2; ++dt) {
-            hipError_t e = launch_batch_pass(dt, s->d_items[dt * P + j], s->d_count[dt * P + j], grid,
-                                             kServeTileQubits[dt], s->stream);
-            if (e != hipSuccess) return e;
-        }
+        for (int w = 0; w < 2; ++w)
+            for (int dt = 0; dt < 2; ++dt) {
+                const int slot = (2 * w + dt) * P + j;
+                hipError_t e = launch_batch_pass(dt, s->d_items[slot], s->d_count[slot], grid, kServeTileQubits[dt],
+                                                 s->stream, w != 0);
+                if (e != hipSuccess) return e;
+            }
     for (int dt = 0; dt < 2; ++dt) {
         hipError_t e = launch_zsum_batch(dt, s->d_z[dt], s->d_zcount + dt, s->d_partial, 1024, s->stream);
         if (e != hipSuccess) return e;
@@ -296,7 +300,7 @@ qsv_status run_step_device(qsv_server s, size_t zdoubles)
     const int P = passes_per_step(s);
     const int slots = std::max(1, s->o.max_slots);
     // work tables to the device (outside the graph)
-    for (int i = 0; i < 2 * P; ++i) {
+    for (int i = 0; i < 4 * P; ++i) {
         const int cnt = *s->h_count[i];
         if (hipMemcpyAsync(s->d_count[i], s->h_count[i], sizeof(int), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
             (cnt > 0 && hipMemcpyAsync(s->d_items[i], s->h_items[i], cnt * sizeof(BatchItem), hipMemcpyHostToDevice,
@@ -384,11 +388,11 @@ qsv_status qsv_server_create(const qsv_server_opts* opts, void* stream, qsv_serv
         }
         s->capacity = s->o.capacity_bytes ? s->o.capacity_bytes : (fr > s->o.reserve_bytes ? fr - s->o.reserve_bytes : 0);
         bool ok = hipEventCreateWithFlags(&s->ev, hipEventDisableTiming) == hipSuccess;
-        s->h_items.assign(2 * P, nullptr);
-        s->d_items.assign(2 * P, nullptr);
-        s->h_count.assign(2 * P, nullptr);
-        s->d_count.assign(2 * P, nullptr);
-        for (int i = 0; ok && i < 2 * P; ++i) {
+        s->h_items.assign(4 * P, nullptr);
+        s->d_items.assign(4 * P, nullptr);
+        s->h_count.assign(4 * P, nullptr);
+        s->d_count.assign(4 * P, nullptr);
+        for (int i = 0; ok && i < 4 * P; ++i) {
             ok = hipHostMalloc((void**)&s->h_items[i], slots * sizeof(BatchItem), hipHostMallocDefault) == hipSuccess &&
                  hipMalloc((void**)&s->d_items[i], slots * sizeof(BatchItem)) == hipSuccess &&
                  hipHostMalloc((void**)&s->h_count[i], sizeof(int), hipHostMallocDefault) == hipSuccess &&
@@ -551,7 +555,7 @@ qsv_status qsv_server_step(qsv_server s, int* n_running, int* n_pending)
     std::vector<std::shared_ptr<Req>> finishing;
     size_t zdoubles = 0;
     if (!s->o.dry_run) {
-        for (int i = 0; i < 2 * P; ++i) *s->h_count[i] = 0;
+        for (int i = 0; i < 4 * P; ++i) *s->h_count[i] = 0;
         s->h_zcount[0] = s->h_zcount[1] = 0;
     }
     long long tiles_step = 0;
@@ -562,7 +566,7 @@ qsv_status qsv_server_step(qsv_server s, int* n_running, int* n_pending)
             const size_t pi = r->next_pass + j;
             tiles_step += hp.pgrid[pi];
             if (s->o.dry_run) continue;
-            const int slot = r->dtype * P + j;
+            const int slot = (2 * (hp.pwide[pi] ? 1 : 0) + r->dtype) * P + j;
             int& cnt = *s->h_count[slot];
             BatchItem& it = s->h_items[slot][cnt];
             it.state = r->state;
