@@ -633,7 +633,73 @@ std::vector<FGate> fuse_commuting(const std::vector<FGate>& gates, int n, const 
     return out;
 }
 
-// Pass scheduling: greedy grouping of the fused ops (in their order) into HBM passes.
+// One pass built greedily from the ops not yet done (in their order).  grow: the tile
+// starts as `A0` and takes the qubits of every op that joins, up to m; otherwise the
+// tile is exactly `A0` and only ops inside it (or diagonal ops) join.  An op joins when
+// none of its qubits is blocked by an earlier deferred op it may not commute with, the
+// tile holds it and the pass's arithmetic budget allows.
+PassPlan build_pass(int n, const std::vector<FGate>& fused, const std::vector<char>& done, const PlanOpts& o,
+                    int m, int L, bool whole, unsigned long long A0, bool grow)
+{
+    const int F = (int)fused.size();
+    const unsigned long long all = (n >= 64) ? ~0ull : ((1ull << n) - 1);
+    PassPlan pp;
+    int Lp = L;   // low qubits kept in this pass's tile
+    unsigned long long A = whole ? all : A0;
+    // qubits of deferred ops: where some deferred op is not diagonal (blocked), and
+    // where all of them are (blocked_d).  A later op may run ahead of the deferred
+    // ones when it touches no blocked qubit and is itself diagonal on every
+    // blocked_d qubit it touches: it then commutes with each of them.
+    unsigned long long blocked = 0, blocked_d = 0;
+    auto defer = [&](unsigned long long gm, unsigned long long gd) {
+        blocked |= gm & ~gd;
+        blocked_d |= gm & gd;
+        blocked_d &= ~blocked;
+    };
+    double budget = o.pass_budget;
+    for (int i = 0; i < F; ++i) {
+        if (done[i]) continue;
+        const FGate& g = fused[i];
+        unsigned long long gm = 0;
+        for (int j = 0; j < g.k; ++j) gm |= 1ull << g.q[j];
+        const unsigned long long gd = o.commute ? g.dq : 0;
+        if ((gm & blocked) || (gm & ~gd & blocked_d)) { defer(gm, gd); continue; }
+        const double c = op_cost(g, o) + o.sigma;
+        const bool limit_ops = o.max_ops_per_pass > 0 && (int)pp.ops.size() >= o.max_ops_per_pass;
+        const bool fits_budget = whole || o.pass_budget < 0 || c <= budget || pp.ops.empty();
+        unsigned long long nA = (g.kind == OP_DIAG) ? A : (A | gm);
+        if (grow && pp.ops.empty() && __builtin_popcountll(nA) > m) {
+            // a gate wider than the tile's free slots opens a pass with fewer low qubits
+            while (Lp > 0 && __builtin_popcountll(gm | ((1ull << Lp) - 1)) > m) --Lp;
+            A = (1ull << Lp) - 1;
+            nA = A | gm;
+        }
+        const bool fits_tile = grow ? __builtin_popcountll(nA) <= m : nA == A;
+        if (!limit_ops && fits_budget && fits_tile) {
+            A = nA;
+            pp.ops.push_back(i);
+            budget -= c;
+            pp.cost += c;
+        } else {
+            defer(gm, gd);
+            if ((blocked & all) == all) break;
+        }
+    }
+    // fill the tile up to m qubits with the lowest unused qubits (longer runs)
+    for (int b = 0; b < n && __builtin_popcountll(A) < m; ++b) A |= 1ull << b;
+    for (int b = 0; b < n; ++b)
+        if ((A >> b) & 1) pp.active.push_back(b);
+    pp.low = Lp;
+    return pp;
+}
+
+// Pass scheduling.  Each pass is the best of several greedy candidates: the tile that
+// grows with the ops in their order, and tiles fixed in advance to the low L qubits
+// plus m - L consecutive others (every window position).  The fixed windows follow the
+// locality of nearest-neighbour circuits: within a window an op can run several layers
+// ahead of the ops outside it, where the growing tile stops at the first op that
+// straddles its edge.  "Best" is the most arithmetic (plus per-op overhead) done, the
+// growing tile winning ties; it always makes progress.
 bool schedule_passes(int n, const std::vector<FGate>& fused, const PlanOpts& o, std::vector<PassPlan>& passes,
                      std::string& err)
 {
@@ -642,64 +708,25 @@ bool schedule_passes(int n, const std::vector<FGate>& fused, const PlanOpts& o, 
     const bool whole = o.fuse && n <= o.whole_state_max;
     const int m = whole ? n : std::min(o.tile_qubits, n);
     const int L = std::min(o.low_qubits, m);
+    const unsigned long long low = (L >= 64) ? ~0ull : ((1ull << L) - 1);
+    const bool windows = !whole && o.fuse == 1 && n > m && m > L;
     std::vector<char> done(F, 0);
     int remaining = F;
-    const unsigned long long all = (n >= 64) ? ~0ull : ((1ull << n) - 1);
     while (remaining > 0) {
-        PassPlan pp;
-        int Lp = L;   // low qubits kept in this pass's tile
-        unsigned long long A = (L >= 64) ? ~0ull : ((1ull << L) - 1);
-        if (whole) A = all;
-        // qubits of deferred ops: where some deferred op is not diagonal (blocked), and
-        // where all of them are (blocked_d).  A later op may run ahead of the deferred
-        // ones when it touches no blocked qubit and is itself diagonal on every
-        // blocked_d qubit it touches: it then commutes with each of them.
-        unsigned long long blocked = 0, blocked_d = 0;
-        auto defer = [&](unsigned long long gm, unsigned long long gd) {
-            blocked |= gm & ~gd;
-            blocked_d |= gm & gd;
-            blocked_d &= ~blocked;
-        };
-        double budget = o.pass_budget;
-        for (int i = 0; i < F; ++i) {
-            if (done[i]) continue;
-            const FGate& g = fused[i];
-            unsigned long long gm = 0;
-            for (int j = 0; j < g.k; ++j) gm |= 1ull << g.q[j];
-            const unsigned long long gd = o.commute ? g.dq : 0;
-            if ((gm & blocked) || (gm & ~gd & blocked_d)) { defer(gm, gd); continue; }
-            const double c = op_cost(g, o) + o.sigma;
-            const bool limit_ops = o.max_ops_per_pass > 0 && (int)pp.ops.size() >= o.max_ops_per_pass;
-            const bool fits_budget = whole || o.pass_budget < 0 || c <= budget || pp.ops.empty();
-            unsigned long long nA = (g.kind == OP_DIAG) ? A : (A | gm);
-            if (pp.ops.empty() && __builtin_popcountll(nA) > m) {
-                // a gate wider than the tile's free slots opens a pass with fewer low qubits
-                while (Lp > 0 && __builtin_popcountll(gm | ((1ull << Lp) - 1)) > m) --Lp;
-                A = (1ull << Lp) - 1;
-                nA = A | gm;
-            }
-            const bool fits_tile = __builtin_popcountll(nA) <= m;
-            if (!limit_ops && fits_budget && fits_tile) {
-                A = nA;
-                pp.ops.push_back(i);
-                done[i] = 1;
-                --remaining;
-                budget -= c;
-                pp.cost += c;
-            } else {
-                defer(gm, gd);
-                if ((blocked & all) == all) break;
+        PassPlan best = build_pass(n, fused, done, o, m, L, whole, low, true);
+        if (windows) {
+            const int w = m - L;
+            for (int a = L; a + w <= n; ++a) {
+                const unsigned long long A0 = low | (((1ull << w) - 1) << a);
+                PassPlan c = build_pass(n, fused, done, o, m, L, whole, A0, false);
+                if (c.cost > best.cost) best = std::move(c);
             }
         }
-        // fill the tile up to m qubits with the lowest unused qubits (longer runs)
-        for (int b = 0; b < n && __builtin_popcountll(A) < m; ++b) A |= 1ull << b;
-        for (int b = 0; b < n; ++b)
-            if ((A >> b) & 1) pp.active.push_back(b);
-        pp.low = Lp;
-        if (pp.ops.empty()) { err = "internal: a gate does not fit any tile"; return false; }
-        passes.push_back(pp);
+        if (best.ops.empty()) { err = "internal: a gate does not fit any tile"; return false; }
+        for (const int i : best.ops) done[i] = 1;
+        remaining -= (int)best.ops.size();
+        passes.push_back(std::move(best));
     }
-
     return true;
 }
 
