@@ -49,7 +49,7 @@ PlanOpts default_opts(int dtype)
         o.tile_qubits = 12;
         o.low_qubits = 4;
         o.whole_state_max = 13;
-        o.pass_budget = 160;
+        o.pass_budget = 224;
         o.sigma = 8;
         o.mfma_min_k = 3;
         o.fp32_mfma = true;
@@ -57,7 +57,7 @@ PlanOpts default_opts(int dtype)
         o.tile_qubits = 12;
         o.low_qubits = 4;
         o.whole_state_max = 12;
-        o.pass_budget = 448;
+        o.pass_budget = 320;
         o.sigma = 8;
         o.mfma_min_k = 3;          // FP64 matrix cores: no faster than FP64 VALU in peak,
         o.mfma_lds_floats = 4096;  // but free of the VALU path's per-row scalar loads
