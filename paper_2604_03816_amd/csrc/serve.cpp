@@ -6,8 +6,8 @@
 // resident matrices and tables + reduction workspace, the terms of the paper's memory
 // model (Eq. 14), against capacity = free device memory at start minus a reserve
 // (Eq. 15).  Each step advances every running request by its next pass(es) in one
-// batched launch per dtype (k_batch_pass: a persistent grid over all running states'
-// tiles), then reduces the requests that finished (per-qubit <Z_i> and norm) in one
+// batched launch per dtype and kernel variant (k_batch_pass: a persistent grid over all
+// running states' tiles; passes without register-heavy ops take the lighter variant), then reduces the requests that finished (per-qubit <Z_i> and norm) in one
 // batched launch, and retires them; requests that arrived meanwhile are admitted at
 // the next step.  The step's launches are captured once in a hipGraph and replayed;
 // only the small work tables change between steps (copied before each replay).
