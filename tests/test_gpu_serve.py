@@ -179,11 +179,13 @@ def test_auto_precision_and_norm_guard(mods):
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_served_circuits_with_diagonal_and_permutation_ops(mods, dtype):
-    """QFT (controlled phases: diagonal tables staged with the pass) and circuits with
-    SWAP / Toffoli (permutations) through the batched kernel."""
+    """QFT (controlled phases: diagonal tables staged with the pass), circuits with
+    SWAP / Toffoli (permutations) and GHZ circuits (CNOT chains fused into 5-qubit
+    permutations: passes for the kernel variant with the wide op paths, in the same steps
+    as passes for the lighter one) through the batched kernel."""
     qsv, serve = mods
     sv = serve.Server(max_slots=8)
-    reqs = [(n, C.qft(n)) for n in (8, 12, 15)]
+    reqs = [(n, C.qft(n)) for n in (8, 12, 15)] + [(n, C.ghz(n)) for n in (14, 17)]
     rng = np.random.default_rng(5)
     for n in (9, 14):
         ops = C.brickwork(n, 4, int(rng.integers(1 << 30)))
