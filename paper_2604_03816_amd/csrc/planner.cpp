@@ -55,7 +55,7 @@ PlanOpts default_opts(int dtype)
         o.fp32_mfma = true;
     } else {            // complex128: 16-byte amplitudes
         o.tile_qubits = 12;
-        o.low_qubits = 4;
+        o.low_qubits = 3;   // 8 contiguous amplitudes: 128-byte runs, as complex64's 16
         o.whole_state_max = 12;
         o.pass_budget = 320;
         o.sigma = 8;
