@@ -6,6 +6,7 @@ sample of amplitudes plus a few reductions are written to JSON next to this scri
 
     python tests/golden/make_golden.py 28      # brickwork n=28 depth=20 seed=2 (4 GiB state)
     python tests/golden/make_golden.py 30      # brickwork n=30 depth=20 seed=3 (16 GiB state)
+    python tests/golden/make_golden.py serve   # served request sizes: n=20, 24, 26 (per-qubit <Z_i>)
 """
 import json
 import os
@@ -21,7 +22,37 @@ import oracle  # noqa: E402
 from paper_2604_03816_amd import circuits as C  # noqa: E402
 
 CASES = {28: (20, 2), 30: (20, 3), 22: (20, 7)}
+# served requests at the large end of the serving workload's 12-26 qubits
+SERVE_CASES = [(20, 30, 21), (24, 20, 22), (26, 15, 23)]
 SAMPLES = 1024
+
+
+def serve_case(n, depth, seed):
+    """Per-qubit <Z_i> and the norm (what a served request returns) plus seeded amplitudes
+    (for states kept on the device) of one brickwork request."""
+    ops = C.brickwork(n, depth, seed)
+    t0 = time.time()
+    psi = oracle.zero_state(n)
+    for op in ops:
+        oracle.apply(psi, oracle.op_matrix(op), op.qubits)
+    rng = np.random.default_rng(777 + n)
+    idx = np.unique(np.concatenate([[0, (1 << n) - 1], rng.integers(0, 1 << n, size=SAMPLES)]))
+    zexp = [float(oracle.pauli_expval(psi, ((q, "Z"),)).real) for q in range(n)]
+    rec = {
+        "about": "FP64 oracle, gate by gate: served brickwork request n=%d depth=%d seed=%d (%d gates); "
+                 "written by tests/golden/make_golden.py" % (n, depth, seed, len(ops)),
+        "n": n, "depth": depth, "seed": seed, "gates": len(ops),
+        "norm2": oracle.norm2(psi),
+        "zexp": zexp,
+        "index": [int(i) for i in idx],
+        "re": [float(a.real) for a in psi[idx]],
+        "im": [float(a.imag) for a in psi[idx]],
+        "oracle_seconds": time.time() - t0,
+    }
+    path = os.path.join(HERE, "serve_brickwork_n%d_d%d_s%d.json" % (n, depth, seed))
+    with open(path, "w") as f:
+        json.dump(rec, f)
+    print("wrote", path, "in %.0f s" % (time.time() - t0))
 
 
 def main(n):
@@ -61,4 +92,8 @@ def main(n):
 
 
 if __name__ == "__main__":
-    main(int(sys.argv[1]))
+    if sys.argv[1] == "serve":
+        for case in SERVE_CASES:
+            serve_case(*case)
+    else:
+        main(int(sys.argv[1]))

@@ -200,3 +200,65 @@ def test_served_circuits_with_diagonal_and_permutation_ops(mods, dtype):
         tol = 1e-12 if dtype == "c128" else 5e-5
         assert r["status"] == 0 and abs(r["norm"] - nrm) <= tol and np.max(np.abs(r["zexp"] - z)) <= tol
     sv.close()
+
+
+def _serve_golden(n, depth, seed):
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "serve_brickwork_n%d_d%d_s%d.json" % (n, depth, seed))
+    with open(path) as f:
+        return json.load(f)
+
+
+SERVE_LARGE = [(20, 30, 21), (24, 20, 22), (26, 15, 23)]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_large_served_requests_against_oracle_alone_and_in_mix(mods, dtype):
+    """Requests at the large end of the served sizes (20, 24 and 26 qubits: 2^14 - 2^15
+    tiles per pass in the batched kernel, 2^12 - 2^14 chunks per state in the batched
+    reduction) against per-qubit <Z_i>, norm and seeded amplitudes the FP64 oracle stored
+    (tests/golden/make_golden.py serve); the 24-qubit request's final state is the same
+    bit for bit alone and in a mix with small requests of both precisions, and within
+    tolerance of the single-state path's."""
+    qsv, serve = mods
+    tol_z = 1e-12 if dtype == "c128" else 5e-5
+    tol_a = 1e-12 if dtype == "c128" else 5e-6
+    gold = {case[0]: _serve_golden(*case) for case in SERVE_LARGE}
+    circ = {n: C.brickwork(n, d, s) for n, d, s in SERVE_LARGE}
+    # alone: the 24-qubit request by itself
+    alone = serve.Server(max_slots=8, keep_states=True)
+    aid = alone.submit(24, dtype, circ[24])
+    ra = [r for r in drain(alone) if r["id"] == aid][0]
+    sa = alone.get_state(aid, 24, dtype)
+    alone.close()
+    # in a mix: small requests of both precisions before, between and after the large ones
+    sv = serve.Server(max_slots=16, keep_states=True)
+    small = mix(11, 18)
+    for n2, dt2, ops2 in small[:6]:
+        sv.submit(n2, dt2, ops2)
+    ids = {}
+    for k, (n, _, _) in enumerate(SERVE_LARGE):
+        ids[sv.submit(n, dtype, circ[n])] = n
+        for n2, dt2, ops2 in small[6 + 4 * k: 10 + 4 * k]:
+            sv.submit(n2, dt2, ops2)
+    res = {r["id"]: r for r in drain(sv)}
+    assert sv.stats()["peak_running"] > 1
+    for rid, n in ids.items():
+        r, g = res[rid], gold[n]
+        assert r["status"] == 0 and r["n"] == n and r["dtype"] == dtype
+        assert abs(r["norm"] - g["norm2"]) <= (1e-12 if dtype == "c128" else 1e-5), (n, r["norm"])
+        err = np.max(np.abs(r["zexp"] - np.array(g["zexp"])))
+        assert err <= tol_z, (n, dtype, err)
+        st = sv.get_state(rid, n, dtype).astype(np.complex128)
+        ref = np.array(g["re"]) + 1j * np.array(g["im"])
+        aerr = np.max(np.abs(st[np.array(g["index"])] - ref))
+        assert aerr <= tol_a, (n, dtype, aerr)
+        if n == 24:
+            assert np.array_equal(st.astype(sa.dtype), sa), "24-qubit state differs between alone and in the mix"
+            assert ra["norm"] == r["norm"] and np.array_equal(ra["zexp"], r["zexp"])
+            s = qsv.State(n, dtype)
+            s.apply(circ[n])
+            assert np.max(np.abs(s.get().astype(np.complex128) - st)) <= tol_a
+            s.free()
+    sv.close()
