@@ -15,7 +15,8 @@ from typing import Iterable, List, Optional, Sequence, Tuple
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "_build", "libqsv.so")
+# QSV_LIB selects another build of the library (the host-sanitizer build of the CPU tests)
+LIB_PATH = os.environ.get("QSV_LIB") or os.path.join(HERE, "_build", "libqsv.so")
 
 QSV_OK, QSV_E_ARG, QSV_E_OOM, QSV_E_DEVICE, QSV_E_UNSUPPORTED = 0, 1, 2, 3, 4
 C64, C128, AUTO = 0, 1, 2
