@@ -13,14 +13,16 @@ value = fused gates x 2 x 2^n x bytes-per-amplitude / step time  ("fused-gate am
 GB/s": every fused gate must read and write each amplitude once; several fused gates
 share one HBM round trip, so the figure can exceed the HBM peak).
 
-roofline: the pass kernel.  Algorithmic bytes per launch = 2 x 2^n x bytes-per-amplitude
-(one read and one write of the state); algorithmic flops per launch = 2 x (the plan's
-complex-arithmetic FMA per amplitude / passes) x 2^n.  The average launch duration comes
-from HIP events recorded around every pass launch inside the timed steps, on the
-state's stream.  The bound reported is the larger fraction: HBM (8 TB/s) or ALU, whose
-peak combines the VALU rate for the VALU share of the FMA (78.6 TFLOP/s: FP64 vector,
-and FP32 without packed math) with the matrix-core rate for the matrix-core share (FP32
-MFMA 157.3 TFLOP/s for complex64, FP64 MFMA 78.6 TFLOP/s for complex128).  traffic = HBM bytes per launch measured with rocprofv3 counters
+roofline: the pass kernel, bound by HBM bandwidth.  Algorithmic bytes per launch = 2 x
+2^n x bytes-per-amplitude (one read and one write of the state; the first pass, which
+builds |0...0> on chip, only writes), averaged over the step's launches, divided by the
+average launch duration (HIP events recorded around every pass launch inside the timed
+steps, on the state's stream) and by the 8 TB/s peak.  Beside it, the ALU fraction of the
+same launches: algorithmic flops per launch = 2 x (the plan's complex-arithmetic FMA per
+amplitude / passes) x 2^n against a peak that combines the VALU rate for the VALU share
+of the FMA (78.6 TFLOP/s: FP64 vector, and FP32 without packed math) with the
+matrix-core rate for the matrix-core share (FP32 MFMA 157.3 TFLOP/s for complex64, FP64
+MFMA 78.6 TFLOP/s for complex128).  traffic = HBM bytes per launch measured with rocprofv3 counters
 (FETCH_SIZE + WRITE_SIZE, scaled by the same counters' reading for a device copy of
 known size), taken from the summary under profiles/ when that summary was made from
 the current kernel source, else null.
@@ -69,6 +71,8 @@ def parse():
     ap.add_argument("--no-sampling", action="store_true")
     ap.add_argument("--no-noise", action="store_true")
     ap.add_argument("--no-commute", action="store_true")
+    ap.add_argument("--kernel-sweep", action="store_true",
+                    help="also time one-op passes per op class (k, targets, VALU vs matrix cores)")
     ap.add_argument("--precision-qubits", type=int, nargs="*", default=[30, 32])
     ap.add_argument("--adjoint-qubits", type=int, default=24)
     ap.add_argument("--adjoint-batch", type=int, default=64)
@@ -183,12 +187,11 @@ def run_dtype(torch, qsv, C, args, dtype, ops, terms):
     hbm_frac = achieved / HBM_PEAK_GBS
     alu_frac = alu_tflops / alu_peak
     traffic = measured_traffic(dtype)
-    if alu_frac > hbm_frac:
-        roof = {"bound": "alu", "achieved": alu_tflops, "peak": alu_peak, "unit": "TFLOP/s",
-                "frac": alu_frac, "traffic": traffic}
-    else:
-        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": hbm_frac, "traffic": traffic}
+    # the pass kernel's roofline is HBM bandwidth (every pass reads and writes the state
+    # once); the ALU fraction of the same launches is reported beside it
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": hbm_frac, "traffic": traffic,
+            "alu": {"achieved": alu_tflops, "peak": alu_peak, "unit": "TFLOP/s", "frac": alu_frac}}
     # sanity of the result: the circuit preserves the norm
     norm = state.norm()
     out = {
@@ -232,7 +235,59 @@ def cpu_baseline(C, args, ops):
     return {"value": value, "unit": "GB/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": "first %d of %d gates of the %d-qubit depth-%d brickwork, complex128, gate by gate "
                       "(%.1f s of gate application; state init %.1f s not counted)"
-                      % (done, len(ops), n, args.depth, t_apply, init_s)}
+                      % (done, len(ops), n, args.depth, t_apply, init_s),
+            "host": host_info(),
+            "one_thread": oracle_one_thread(24, args.depth, args.seed, min(5.0, args.cpu_seconds))}
+
+
+def host_info():
+    """CPU model, logical CPUs and RAM of the host the oracle ran on."""
+    info = {"logical_cpus": os.cpu_count()}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    info["ram_gib"] = round(int(line.split()[1]) / 2 ** 20, 1)
+                    break
+    except OSError:
+        pass
+    return info
+
+
+_ONE_THREAD = r"""
+import json, sys, time
+sys.path.insert(0, sys.argv[1])
+import oracle
+from paper_2604_03816_amd import circuits as C
+n, depth, seed, budget = int(sys.argv[2]), int(sys.argv[3]), int(sys.argv[4]), float(sys.argv[5])
+ops = C.brickwork(n, depth, seed)
+psi = oracle.zero_state(n)
+done, t = 0, 0.0
+while done < len(ops) and t < budget:
+    t0 = time.perf_counter()
+    oracle.apply(psi, oracle.op_matrix(ops[done]), ops[done].qubits)
+    t += time.perf_counter() - t0
+    done += 1
+print(json.dumps({"n": n, "gates": done, "seconds": t, "threads": oracle.num_threads(),
+                  "GB_per_s": done * 2.0 * 2 ** n * 16 / t / 1e9, "ms_per_gate": t / done * 1e3}))
+"""
+
+
+def oracle_one_thread(n, depth, seed, budget):
+    """The oracle on one host thread (a child process with OMP_NUM_THREADS=1) on the first
+    gates of the n-qubit brickwork: the shape of a single-threaded CPU simulator column."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", _ONE_THREAD, ROOT, str(n), str(depth), str(seed), str(budget)],
+                       env=env, capture_output=True, text=True, timeout=300)
+    if r.returncode != 0:
+        return {"error": r.stderr[-500:]}
+    return json.loads(r.stdout.strip().splitlines()[-1])
 
 
 def serving(args):
@@ -296,22 +351,33 @@ def precision_study(args):
                        "expval_ms": t_red * 1e3, "passes": plan.stats()["passes"]}
             states[dt] = s
             plan.free()
-        a = states["c128"].tensor
-        b = states["c64"].tensor
-        # fidelity |<psi128|psi64>|^2 accumulated in FP64 chunk by chunk (no full-size copy)
-        ov = 0j
-        step = 1 << 26
-        for i in range(0, a.numel(), step):
-            ov += torch.vdot(a[i:i + step], b[i:i + step].to(torch.complex128)).item()
+        gap = precision_gap(states["c128"].tensor, states["c64"].tensor)
         rec["c64_vs_c128"] = {"d_zz": abs(rec["c64"]["zz"] - rec["c128"]["zz"]),
-                              "d_x": abs(rec["c64"]["x"] - rec["c128"]["x"]),
-                              "fidelity_deficit": 1.0 - abs(ov) ** 2}
+                              "d_x": abs(rec["c64"]["x"] - rec["c128"]["x"]), **gap}
         for st in states.values():
             st.free()
         del a, b, states
         torch.cuda.empty_cache()
         out.append(rec)
     return out
+
+
+def precision_gap(a, b, chunk=1 << 26):
+    """complex64 state b against the complex128 state a of the same circuit over the whole
+    state, chunk by chunk on the device in FP64: max |a_k - b_k|, the raw overlap deficit
+    1 - |<a|b>|^2 (which follows b's norm drift) and the normalised infidelity
+    1 - |<a|b>|^2 / (<a|a> <b|b>) (the state error proper)."""
+    import torch
+    ov, na, nb, mx = 0j, 0.0, 0.0, 0.0
+    for i in range(0, a.numel(), chunk):
+        x = a[i:i + chunk]
+        y = b[i:i + chunk].to(torch.complex128)
+        ov += torch.vdot(x, y).item()
+        na += torch.vdot(x, x).real.item()
+        nb += torch.vdot(y, y).real.item()
+        mx = max(mx, (x - y).abs().max().item())
+    return {"max_abs_diff": mx, "raw_deficit": 1.0 - abs(ov) ** 2,
+            "infidelity": 1.0 - abs(ov) ** 2 / (na * nb), "norm2_c64_minus_1": nb - 1.0}
 
 
 def commutation_bench(args):
@@ -356,7 +422,9 @@ def commutation_bench(args):
 def adjoint_bench(args):
     """Adjoint gradients: 24-qubit ansatz, 8 layers of RY, RZ + CZ ring (384 parameters),
     transverse-field Ising H (periodic, h = 0.7), 64 parameter vectors; complex128 and
-    complex64.  Reports wall time per batch and a central-difference spot check."""
+    complex64.  Reports wall time per batch, a central-difference spot check and the
+    complex64 gradients' error against complex128."""
+    import numpy as np
     from paper_2604_03816_amd import circuits as C
     from paper_2604_03816_amd import qsv
     n, layers, B = args.adjoint_qubits, 8, args.adjoint_batch
@@ -370,7 +438,9 @@ def adjoint_bench(args):
         wall = time.perf_counter() - t0
         out[dt] = {"wall_s": wall, "gradients_per_s": B * params.shape[1] / wall, "energy0": float(E[0])}
         if dt == "c128":
-            g128 = G
+            g128 = np.asarray(G)
+        else:
+            g64 = np.asarray(G)
     # central differences (h = 1e-6, complex128 energies) on 4 parameters of vector 0
     h = 1e-6
     idx = [0, 57, 200, 383 if params.shape[1] > 383 else params.shape[1] - 1]
@@ -383,6 +453,11 @@ def adjoint_bench(args):
         em, _ = qsv.adjoint_grad(n, tpl, p, terms, "c128")
         fd.append((ep - em) / (2 * h))
     out["fd_check"] = {"params": idx, "max_abs_diff": float(max(abs(g128[0][j] - f) for j, f in zip(idx, fd)))}
+    # complex64 gradients against complex128: relative error ||g64 - g128|| / ||g128|| per
+    # parameter vector (the worst and the median over the batch) and the largest element error
+    rel = np.linalg.norm(g64 - g128, axis=1) / np.linalg.norm(g128, axis=1)
+    out["c64_vs_c128"] = {"rel_err_max": float(rel.max()), "rel_err_median": float(np.median(rel)),
+                          "max_abs_diff": float(np.max(np.abs(g64 - g128)))}
     return out
 
 
@@ -411,6 +486,61 @@ def sampling_bench(args, ops):
     plan.free()
     torch.cuda.empty_cache()
     return out
+
+
+def kernel_sweep(args):
+    """Pass kernel per op class at n qubits: one fused op per pass (a Haar k-qubit unitary,
+    k = 1..5, or a diagonal 5-qubit phase table) on targets at the bottom of the index
+    (qubits 0..k-1, inside the tile's contiguous runs), in the middle (qubits 4..3+k, tile
+    qubits outside the runs) or at the top (n-k..n-1, strided tile rows); dense ops of
+    3 and 4 qubits both on the VALU and on matrix cores.  Median of 5 launches (HIP events
+    on the state's stream) after 2 warm-up launches; GB/s = 2 x 2^n x bytes-per-amplitude
+    per launch."""
+    import numpy as np
+    import torch
+    from paper_2604_03816_amd import circuits as C
+    from paper_2604_03816_amd import qsv
+    n = args.qubits
+    rng = np.random.default_rng(9)
+    where = {"low": lambda k: tuple(range(k)), "mid": lambda k: tuple(range(4, 4 + k)),
+             "high": lambda k: tuple(range(n - k, n))}
+    rows = []
+    for dt in ("c64", "c128"):
+        s = qsv.State(n, dt)
+        elem = 8 if dt == "c64" else 16
+
+        def timed(ops, mc):
+            plan = qsv.Plan(n, dt, ops, matrix_cores=mc)
+            st = plan.stats()
+            ts = []
+            for i in range(7):
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record(s.stream)
+                s.apply_plan(plan)
+                b.record(s.stream)
+                b.synchronize()
+                if i >= 2:
+                    ts.append(a.elapsed_time(b))
+            plan.free()
+            ms = sorted(ts)[len(ts) // 2]
+            gbs = 2.0 * (2 ** n) * elem / (ms * 1e-3) / 1e9
+            return {"ms": ms, "GB_per_s": gbs, "hbm_frac": gbs / HBM_PEAK_GBS, "passes": st["passes"],
+                    "mfma_ops": st["mfma_ops"]}
+
+        for k in range(1, 6):
+            U = C.haar_unitary(rng, 1 << k)
+            for cls, tg in where.items():
+                ops = [C.Op("U", tg(k), matrix=U)]
+                engines = (("valu", -1), ("mfma", 3)) if k in (3, 4) else (("valu", -1),)
+                for eng, mc in engines:
+                    rows.append(dict(dtype=dt, op="dense", k=k, targets=cls, engine=eng, **timed(ops, mc)))
+        D = np.diag(np.exp(1j * rng.uniform(0, 2 * math.pi, 32)))
+        for cls, tg in where.items():
+            rows.append(dict(dtype=dt, op="diag", k=5, targets=cls, engine="valu", **timed([C.Op("U", tg(5), matrix=D)], -1)))
+        s.free()
+        torch.cuda.empty_cache()
+    return {"n": n, "rows": rows}
 
 
 def noise_bench(args):
@@ -508,6 +638,8 @@ def main():
         rec["noise"] = noise_bench(args)
     if not args.no_commute:
         rec["commutation"] = commutation_bench(args)
+    if args.kernel_sweep:
+        rec["kernel_sweep"] = kernel_sweep(args)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(C, args, ops)
     print(json.dumps(rec))

@@ -184,8 +184,12 @@ qsv_status qsv_plan_apply_range(qsv_state s, qsv_plan p, size_t first, size_t co
  * like qsv_plan_apply. */
 qsv_status qsv_plan_apply_zero(qsv_state s, qsv_plan p, size_t count);
 
-/* One call = plan + apply + release; synchronises the stream before returning.
- * stats may be NULL. */
+/* One call = plan + apply + release: the gate sequence applied in order to the state
+ * (Section 3 and Eq. 10), fused by Algorithm 2 (Section 5.2) under `opts` (NULL = the
+ * defaults of qsv_plan_create), then scheduled into HBM passes.  stats (may be NULL)
+ * receives the plan's counts: gates in, fused gates out, passes, algorithmic HBM bytes.
+ * Synchronises the stream before returning.  Errors: as qsv_plan_create, plus
+ * QSV_E_DEVICE. */
 qsv_status qsv_apply_fused(qsv_state s, const qsv_gate* gates, size_t n_gates,
                            const qsv_plan_opts* opts, qsv_plan_stats* stats);
 
@@ -209,7 +213,11 @@ typedef struct {
 
 /* <psi|P_t|psi> for every term (Hermitian Pauli strings, real result), evaluated in
  * as few read passes over the state as the terms allow, FP64 accumulation with a
- * compensated, fixed-order combination.  per_term (host, n_terms doubles) receives
+ * compensated, fixed-order combination.  Expectation values are one of the core
+ * operations of a state-vector library (Section 2.2); the definition used is the
+ * textbook one: with x the bit mask of the term's X and Y qubits, z that of its Z and Y
+ * qubits and n_Y its number of Y factors (Y = i X Z),
+ *     <psi|P|psi> = sum_k conj(alpha_{k xor x}) * i^{n_Y} * (-1)^{popcount(k and z)} * alpha_k.  per_term (host, n_terms doubles) receives
  * coeff_t * <P_t>; sum (host) receives their compensated sum.  Either may be NULL.
  * Synchronous.  Errors: QSV_E_ARG for bad qubits or letters. */
 qsv_status qsv_expval_pauli(qsv_state s, const qsv_pauli_term* terms, size_t n_terms,

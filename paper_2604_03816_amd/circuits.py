@@ -27,7 +27,7 @@ from typing import List, Optional, Sequence, Tuple
 import numpy as np
 
 __all__ = [
-    "Op", "haar_u2", "brickwork", "brickwork_arrays", "ghz", "hea", "hea_params", "qft", "random_1q",
+    "Op", "haar_u2", "haar_unitary", "brickwork", "brickwork_arrays", "ghz", "hea", "hea_params", "qft", "random_1q",
     "tfim_terms", "zz_chain_terms", "x_sum_terms", "bind", "inverse_ops",
     "serving_stream", "Request", "with_depolarizing", "CHANNELS", "h_t_cz_bricks", "commuting_mix",
 ]
@@ -183,10 +183,14 @@ def h_t_cz_bricks(n: int, depth: int, seed: int) -> List[Op]:
     return ops
 
 
-def _haar(rng: np.random.Generator, d: int) -> np.ndarray:
+def haar_unitary(rng: np.random.Generator, d: int) -> np.ndarray:
+    """A Haar-random d x d unitary: QR of a complex Gaussian with Mezzadri's phase fix."""
     z = rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d))
     q, r = np.linalg.qr(z)
     return q * (np.diag(r) / np.abs(np.diag(r)))
+
+
+_haar = haar_unitary
 
 
 def commuting_mix(n: int, count: int, seed: int) -> List[Op]:
