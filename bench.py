@@ -71,6 +71,7 @@ def parse():
     ap.add_argument("--no-sampling", action="store_true")
     ap.add_argument("--no-noise", action="store_true")
     ap.add_argument("--no-commute", action="store_true")
+    ap.add_argument("--no-fusion", action="store_true")
     ap.add_argument("--kernel-sweep", action="store_true",
                     help="also time one-op passes per op class (k, targets, VALU vs matrix cores)")
     ap.add_argument("--precision-qubits", type=int, nargs="*", default=[30, 32])
@@ -488,6 +489,57 @@ def sampling_bench(args, ops):
     return out
 
 
+def fusion_bench(args):
+    """The fusion study at 28 qubits: the seeded brickwork (depth 20, seed 2, 830 gates)
+    fused by the DAG planner (<= 5-qubit unitaries, several per HBM pass) against the
+    same circuit unfused and gate by gate (one gate per pass, as the paper applies gates),
+    in complex64 and complex128.  Per run: gates, fused gates, passes, the median of 3
+    applications to |0...0> (HIP events), fused-gate amplitude GB/s and HBM GB/s, and
+    max |d alpha| against the FP64 oracle's amplitudes at 1 026 seeded indices (stored by
+    tests/golden/make_golden.py, which also records the oracle's own run time)."""
+    import numpy as np
+    import torch
+    from paper_2604_03816_amd import circuits as C
+    from paper_2604_03816_amd import qsv
+    n, depth, seed = 28, 20, 2
+    with open(os.path.join(ROOT, "tests", "golden", "brickwork_n%d_d%d_s%d.json" % (n, depth, seed))) as f:
+        g = json.load(f)
+    ref = np.array(g["re"]) + 1j * np.array(g["im"])
+    ops = C.brickwork(n, depth, seed)
+    out = {"n": n, "depth": depth, "seed": seed, "gates": len(ops),
+           "oracle": {"seconds": g.get("oracle_seconds"), "threads": g.get("oracle_threads"),
+                      "samples": len(g["index"])}}
+    for dt in ("c64", "c128"):
+        s = qsv.State(n, dt)
+        elem = 8 if dt == "c64" else 16
+        idx = torch.tensor(g["index"], dtype=torch.int64, device=s.tensor.device)
+        rec = {}
+        for label, fuse in (("fused", 1), ("unfused", 0)):
+            plan = qsv.Plan(n, dt, ops, fuse=fuse)
+            st = plan.stats()
+            ts = []
+            for _ in range(3):
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record(s.stream)
+                s.apply_plan_zero(plan)
+                b.record(s.stream)
+                b.synchronize()
+                ts.append(a.elapsed_time(b) * 1e-3)
+            t = sorted(ts)[1]
+            amps = s.tensor[idx].cpu().numpy().astype(np.complex128)
+            rec[label] = {"fused_gates": st["fused_out"], "passes": st["passes"], "seconds": t,
+                          "fused_gate_GB_per_s": st["fused_out"] * 2.0 * 2 ** n * elem / t / 1e9,
+                          "hbm_GB_per_s": (2.0 * st["passes"] - 1.0) * 2 ** n * elem / t / 1e9,
+                          "max_abs_diff_vs_oracle": float(np.max(np.abs(amps - ref)))}
+            plan.free()
+        rec["speedup"] = rec["unfused"]["seconds"] / rec["fused"]["seconds"]
+        out[dt] = rec
+        s.free()
+        torch.cuda.empty_cache()
+    return out
+
+
 def kernel_sweep(args):
     """Pass kernel per op class at n qubits: one fused op per pass (a Haar k-qubit unitary,
     k = 1..5, or a diagonal 5-qubit phase table) on targets at the bottom of the index
@@ -638,6 +690,8 @@ def main():
         rec["noise"] = noise_bench(args)
     if not args.no_commute:
         rec["commutation"] = commutation_bench(args)
+    if not args.no_fusion:
+        rec["fusion"] = fusion_bench(args)
     if args.kernel_sweep:
         rec["kernel_sweep"] = kernel_sweep(args)
     if not args.no_cpu:

@@ -109,10 +109,11 @@ __device__ __forceinline__ long long local_stride(const PassArgs& a, int i)
     return 1ll << a.phys[i];   // i is a compile-time constant at every call site
 }
 
-template <typename C, bool LOAD, int NS, int W>
+template <typename C, bool LOAD, int NS, int W, int NT = kThreads>
 __device__ __forceinline__ void move_tile_n(gptr<C> __restrict__ st, C* __restrict__ lds, const PassArgs& a,
                                             long long toff)
 {
+    constexpr int LOGT = NT == 512 ? 9 : 8;
     static_assert(W == 1 || (W == 2 && sizeof(C) == 8), "16-byte lanes");
     using V = typename std::conditional<W == 2, floatx4, C>::type;
     // the state streams through once per pass: nontemporal loads and stores (measured
@@ -122,12 +123,12 @@ __device__ __forceinline__ void move_tile_n(gptr<C> __restrict__ st, C* __restri
     constexpr int LB = NS >= 32 ? 5 : NS >= 16 ? 4 : NS >= 8 ? 3 : NS >= 4 ? 2 : NS >= 2 ? 1 : 0;
     long long hs[LB > 0 ? LB : 1];
 #pragma unroll
-    for (int b = 0; b < LB; ++b) hs[b] = local_stride(a, kLogThreads + LW + b);
+    for (int b = 0; b < LB; ++b) hs[b] = local_stride(a, LOGT + LW + b);
     const int tid = threadIdx.x;
     V v[NS];
     V* l = reinterpret_cast<V*>(lds);
-    // 16-byte unit u = 256 j + tid holds tile elements W u .. W u + W - 1
-    auto unit = [&](int j) { return (j << kLogThreads) + tid; };
+    // 16-byte unit u = NT j + tid holds tile elements W u .. W u + W - 1
+    auto unit = [&](int j) { return (j << LOGT) + tid; };
     if (LOAD) {
 #pragma unroll
         for (int j = 0; j < NS; ++j) {
@@ -217,13 +218,13 @@ __device__ __forceinline__ int group_base(int g, const DevOp& op)
     return b;
 }
 
-template <typename C, int K>
+template <typename C, int K, int NT = kThreads>
 __device__ void op_dense(C* __restrict__ lds, int T, const DevOp& op, cptr<C> __restrict__ M)
 {
     constexpr int D = 1 << K;
     const int G = T >> K;
     const int bt = group_base<K>(threadIdx.x, op);
-    for (int g0 = 0; g0 < G; g0 += kThreads) {
+    for (int g0 = 0; g0 < G; g0 += NT) {
         if (g0 + (int)threadIdx.x >= G) break;
         // b = group_base(g0) | group_base(tid): the uniform part is scalar work
         const int b = group_base<K>(g0, op) | bt;
@@ -257,14 +258,16 @@ __device__ void op_dense(C* __restrict__ lds, int T, const DevOp& op, cptr<C> __
 // own disjoint groups.
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
-template <typename C, int K>
+template <typename C, int K, int NT = kThreads>
 __device__ void op_dense_mfma(C* __restrict__ lds, int T, const DevOp& op, const float* __restrict__ Araw)
 {
     using R = typename std::conditional<sizeof(C) == 8, float, double>::type;
     using Acc = typename std::conditional<sizeof(C) == 8, floatx4, doublex4>::type;
     const R* __restrict__ A = reinterpret_cast<const R*>(Araw);
     constexpr int D = 1 << K, R2 = 2 * D, RB = R2 / 16, KS = R2 / 4;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // the wave index is uniform: saying so keeps the block loop's bookkeeping and each
+    // block's group base on the scalar unit
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     const int q = lane >> 4, col = lane & 15;
     R a[RB][KS];
 #pragma unroll
@@ -282,39 +285,64 @@ __device__ void op_dense_mfma(C* __restrict__ lds, int T, const DevOp& op, const
     }
     const int nblk = (T >> K) >> 4;
     const int bcol = group_base<K>(col, op);
-    for (int blk = wave; blk < nblk; blk += kThreads / 64) {
-        const int sb = group_base<K>(blk << 4, op) | bcol;
-        Acc acc[RB];
+    // two blocks per iteration (blocks blk and blk + waves): their LDS reads are issued
+    // together and their accumulation chains interleave on the matrix pipe
+    constexpr int NW = NT / 64, U = 2;
+    for (int blk = wave; blk < nblk; blk += U * NW) {
+        int sb[U];
+        bool live[U];
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb) acc[rb] = Acc{0, 0, 0, 0};
+        for (int u = 0; u < U; ++u) {
+            const int b = blk + u * NW;
+            live[u] = b < nblk;   // uniform
+            // the block's part of the group base is uniform (scalar unit); the lane's
+            // part was computed once
+            sb[u] = __builtin_amdgcn_readfirstlane(group_base<K>((live[u] ? b : blk) << 4, op)) | bcol;
+        }
+        C v[U][KS / 2];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int j = 0; j < KS / 2; ++j) v[u][j] = lds[sb[u] | rin[j]];
+        Acc acc[U][RB];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) acc[u][rb] = Acc{0, 0, 0, 0};
 #pragma unroll
         for (int j = 0; j < KS / 2; ++j) {
-            const C v = lds[sb | rin[j]];
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) {
-                if constexpr (sizeof(C) == 8) {
-                    acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][2 * j], v.x, acc[rb], 0, 0, 0);
-                    acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][2 * j + 1], v.y, acc[rb], 0, 0, 0);
-                } else {
-                    acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb][2 * j], v.x, acc[rb], 0, 0, 0);
-                    acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb][2 * j + 1], v.y, acc[rb], 0, 0, 0);
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if constexpr (sizeof(C) == 8) {
+                        acc[u][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][2 * j], v[u][j].x, acc[u][rb], 0, 0, 0);
+                        acc[u][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][2 * j + 1], v[u][j].y, acc[u][rb], 0, 0, 0);
+                    } else {
+                        acc[u][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb][2 * j], v[u][j].x, acc[u][rb], 0, 0, 0);
+                        acc[u][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb][2 * j + 1], v[u][j].y, acc[u][rb], 0, 0, 0);
+                    }
                 }
             }
         }
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-            C o0, o1;
-            o0.x = acc[rb][0];
-            o0.y = acc[rb][1];
-            o1.x = acc[rb][2];
-            o1.y = acc[rb][3];
-            lds[sb | rout[2 * rb]] = o0;
-            lds[sb | rout[2 * rb + 1]] = o1;
+        for (int u = 0; u < U; ++u) {
+            if (!live[u]) continue;
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                C o0, o1;
+                o0.x = acc[u][rb][0];
+                o0.y = acc[u][rb][1];
+                o1.x = acc[u][rb][2];
+                o1.y = acc[u][rb][3];
+                lds[sb[u] | rout[2 * rb]] = o0;
+                lds[sb[u] | rout[2 * rb + 1]] = o1;
+            }
         }
     }
 }
 
-template <typename C, int K>
+template <typename C, int K, int NT = kThreads>
 __device__ void op_perm(C* __restrict__ lds, int T, const DevOp& op, cptr<C> __restrict__ ph,
                         cptr<int> __restrict__ src)
 {
@@ -322,7 +350,7 @@ __device__ void op_perm(C* __restrict__ lds, int T, const DevOp& op, cptr<C> __r
     const int G = T >> K;
     const bool phased = op.flags != 0;
     const int bt = group_base<K>(threadIdx.x, op);
-    for (int g0 = 0; g0 < G; g0 += kThreads) {
+    for (int g0 = 0; g0 < G; g0 += NT) {
         if (g0 + (int)threadIdx.x >= G) break;
         const int b = group_base<K>(g0, op) | bt;
         C v[D];
@@ -336,7 +364,7 @@ __device__ void op_perm(C* __restrict__ lds, int T, const DevOp& op, cptr<C> __r
 // Diagonal op: the table (2^k phases) is read from LDS when the planner staged it there
 // (per-lane indices; a global read here would also wait on every outstanding memory
 // operation of the pass), else from the plan pool.
-template <typename C, typename P>
+template <typename C, typename P, int NT = kThreads>
 __device__ __forceinline__ void op_diag(C* __restrict__ lds, int T, const DevOp& op, P Dg, long long base)
 {
     // targets outside the tile contribute a per-tile constant part of the table index
@@ -346,7 +374,7 @@ __device__ __forceinline__ void op_diag(C* __restrict__ lds, int T, const DevOp&
         lp[j] = (j < op.k) ? op.lpos[j] : -1;
         if (j < op.k && lp[j] < 0) gfix |= (int)((base >> op.gbit[j]) & 1) << j;
     }
-    for (int e = threadIdx.x; e < T; e += kThreads) {
+    for (int e = threadIdx.x; e < T; e += NT) {
         int idx = gfix;
 #pragma unroll
         for (int j = 0; j < kMaxDiagK; ++j)
@@ -355,10 +383,20 @@ __device__ __forceinline__ void op_diag(C* __restrict__ lds, int T, const DevOp&
     }
 }
 
+// Workgroup barrier for LDS data only: waits for this wave's LDS operations, then for
+// every wave of the workgroup.  Unlike __syncthreads it does not wait for outstanding
+// global memory operations (between two ops of a pass only LDS data changes hands).
+// The memory clobber keeps the compiler from moving LDS accesses across it.
+__device__ __forceinline__ void lds_sync()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 // WIDE = false leaves out the register-heavy paths (VALU dense ops on 4 or 5 targets,
 // permutations on 3 or more): the caller launches that variant only for passes without
-// such ops, and its lower register count allows more resident workgroups.
-template <typename C, bool WIDE = true>
+// such ops, and its lower register count allows more resident workgroups.  NT is the
+// workgroup size.  Ends with an LDS barrier after the last op.
+template <typename C, bool WIDE = true, int NT = kThreads>
 __device__ __forceinline__ void apply_ops(C* __restrict__ lds, int T, cptr<DevOp> __restrict__ ops, int op_begin,
                           int op_count, cptr<C> __restrict__ pool, cptr<int> __restrict__ ipool,
                           const float* __restrict__ alds, long long base)
@@ -367,45 +405,45 @@ __device__ __forceinline__ void apply_ops(C* __restrict__ lds, int T, cptr<DevOp
         const DevOp op = ops[op_begin + oi];
         cptr<C> M = pool + op.off;
         if (op.kind == OP_DENSE && op.aoff >= 0) {
-            // the planner gives matrix cores 3- and 4-qubit ops only (a 5-qubit operand
-            // block exceeds the per-pass LDS operand budget)
-            if (op.k == 3) op_dense_mfma<C, 3>(lds, T, op, alds + op.aoff);
-            else op_dense_mfma<C, 4>(lds, T, op, alds + op.aoff);
-            __syncthreads();
+            // the planner gives matrix cores 3- and 4-qubit ops only
+            if (op.k == 3) op_dense_mfma<C, 3, NT>(lds, T, op, alds + op.aoff);
+            else op_dense_mfma<C, 4, NT>(lds, T, op, alds + op.aoff);
+            lds_sync();
             continue;
         }
         if (op.kind == OP_DENSE) {
             switch (op.k) {
-            case 1: op_dense<C, 1>(lds, T, op, M); break;
-            case 2: op_dense<C, 2>(lds, T, op, M); break;
-            case 3: op_dense<C, 3>(lds, T, op, M); break;
-            case 4: if constexpr (WIDE) op_dense<C, 4>(lds, T, op, M); break;
-            default: if constexpr (WIDE) op_dense<C, 5>(lds, T, op, M); break;
+            case 1: op_dense<C, 1, NT>(lds, T, op, M); break;
+            case 2: op_dense<C, 2, NT>(lds, T, op, M); break;
+            case 3: op_dense<C, 3, NT>(lds, T, op, M); break;
+            case 4: if constexpr (WIDE) op_dense<C, 4, NT>(lds, T, op, M); break;
+            default: if constexpr (WIDE) op_dense<C, 5, NT>(lds, T, op, M); break;
             }
         } else if (op.kind == OP_PERM) {
             cptr<int> S = ipool + op.ioff;
             switch (op.k) {
-            case 1: op_perm<C, 1>(lds, T, op, M, S); break;
-            case 2: op_perm<C, 2>(lds, T, op, M, S); break;
-            case 3: if constexpr (WIDE) op_perm<C, 3>(lds, T, op, M, S); break;
-            case 4: if constexpr (WIDE) op_perm<C, 4>(lds, T, op, M, S); break;
-            default: if constexpr (WIDE) op_perm<C, 5>(lds, T, op, M, S); break;
+            case 1: op_perm<C, 1, NT>(lds, T, op, M, S); break;
+            case 2: op_perm<C, 2, NT>(lds, T, op, M, S); break;
+            case 3: if constexpr (WIDE) op_perm<C, 3, NT>(lds, T, op, M, S); break;
+            case 4: if constexpr (WIDE) op_perm<C, 4, NT>(lds, T, op, M, S); break;
+            default: if constexpr (WIDE) op_perm<C, 5, NT>(lds, T, op, M, S); break;
             }
         } else if (op.aoff >= 0) {
-            op_diag<C>(lds, T, op, reinterpret_cast<const C*>(alds + op.aoff), base);
+            op_diag<C, const C*, NT>(lds, T, op, reinterpret_cast<const C*>(alds + op.aoff), base);
         } else {
-            op_diag<C>(lds, T, op, M, base);
+            op_diag<C, cptr<C>, NT>(lds, T, op, M, base);
         }
-        __syncthreads();
+        lds_sync();
     }
 }
 
 // The pass's MFMA operand block, global -> LDS (once per workgroup, or per work item in
 // batched launches).
+template <int NT = kThreads>
 __device__ __forceinline__ void stage_operands(float* __restrict__ alds, cptr<float> __restrict__ apool,
                                                const PassArgs& a)
 {
-    for (int i = threadIdx.x; i < a.a_len; i += kThreads) alds[i] = apool[a.a_off + i];
+    for (int i = threadIdx.x; i < a.a_len; i += NT) alds[i] = apool[a.a_off + i];
 }
 
 // One tile of one pass: HBM -> LDS, every op of the pass, LDS -> HBM.
@@ -1184,6 +1222,7 @@ hipError_t launch_pass_t(void* st, void* st2, const PassArgs& a, long long ntile
                          const void* pool, const int* ipool, const float* apool, hipStream_t s, bool from_zero)
 {
     using C = typename CT<R>::T;
+    const long long total = st2 ? 2 * ntiles : ntiles;
     static bool attr_set = false;
     if (!attr_set) {
         // a 64 KiB complex128 tile plus its operand block exceeds the 64 KiB default
@@ -1195,7 +1234,7 @@ hipError_t launch_pass_t(void* st, void* st2, const PassArgs& a, long long ntile
     // at most 64 workgroups per CU, each striding over tiles: the operand block is staged
     // once per workgroup rather than once per tile (measured on 2^18-tile passes: 6 %
     // faster for complex64, 10 % for complex128 than one workgroup per tile)
-    const long long grid = std::min<long long>(st2 ? 2 * ntiles : ntiles, 64ll * device_cus());
+    const long long grid = std::min<long long>(total, 64ll * device_cus());
     hipLaunchKernelGGL(k_pass<C>, dim3((unsigned)grid), dim3(kThreads), lds, s, (C*)st, (C*)st2, a, ntiles,
                        from_zero ? 1 : 0, ops, (const C*)pool, ipool, apool);
     return hipGetLastError();
