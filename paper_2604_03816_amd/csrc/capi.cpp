@@ -543,7 +543,7 @@ qsv_status enqueue_plan(qsv_state s, const HostPlan& hp, qsv_state s2 = nullptr,
     for (size_t i = 0; i < hp.passes.size(); ++i)
         QSV_HIP(launch_pass(s->dtype, s->buf, hp.pargs[i], hp.pgrid[i], (const DevOp*)(d + o_ops), d + o_pool,
                             (const int*)(d + o_ipool), (const float*)(d + o_apool), s->stream,
-                            s2 ? s2->buf : nullptr, from_zero && i == 0));
+                            s2 ? s2->buf : nullptr, from_zero && i == 0, hp.pwide[i] != 0));
     return QSV_OK;
 }
 
@@ -900,7 +900,7 @@ qsv_status qsv_plan_apply_range(qsv_state s, qsv_plan p, size_t first, size_t co
     for (size_t i = first; i < first + count; ++i) {
         const PassArgs& a = p->hp.pargs[i];
         QSV_HIP(launch_pass(s->dtype, s->buf, a, p->hp.pgrid[i], p->d_ops, p->d_pool, p->d_ipool, p->d_apool,
-                            s->stream));
+                            s->stream, nullptr, false, p->hp.pwide[i] != 0));
     }
     return QSV_OK;
 }
@@ -923,7 +923,7 @@ qsv_status qsv_plan_apply_zero(qsv_state s, qsv_plan p, size_t count)
     for (size_t i = 0; i < count; ++i) {
         const PassArgs& a = p->hp.pargs[i];
         QSV_HIP(launch_pass(s->dtype, s->buf, a, p->hp.pgrid[i], p->d_ops, p->d_pool, p->d_ipool, p->d_apool,
-                            s->stream, nullptr, i == 0));
+                            s->stream, nullptr, i == 0, p->hp.pwide[i] != 0));
     }
     return QSV_OK;
 }

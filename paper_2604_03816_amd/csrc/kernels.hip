@@ -125,64 +125,68 @@ __device__ __forceinline__ void move_tile_n(gptr<C> __restrict__ st, C* __restri
 #pragma unroll
     for (int b = 0; b < LB; ++b) hs[b] = local_stride(a, LOGT + LW + b);
     const int tid = threadIdx.x;
-    V v[NS];
+    // at most CH 16-byte units in registers at a time: wider tiles move in several
+    // batches, so the largest tile does not set the kernel's register count
+    constexpr int CH = NS < 8 ? NS : 8;
+    V v[CH];
     V* l = reinterpret_cast<V*>(lds);
     // 16-byte unit u = NT j + tid holds tile elements W u .. W u + W - 1
     auto unit = [&](int j) { return (j << LOGT) + tid; };
-    if (LOAD) {
+    auto off = [&](int j) {
+        long long so = 0;
 #pragma unroll
-        for (int j = 0; j < NS; ++j) {
-            long long so = 0;
+        for (int b = 0; b < LB; ++b)
+            if ((j >> b) & 1) so += hs[b];
+        return so;
+    };
 #pragma unroll
-            for (int b = 0; b < LB; ++b)
-                if ((j >> b) & 1) so += hs[b];
-            v[j] = __builtin_bit_cast(V, __builtin_nontemporal_load((const NV*)(st + toff + so)));
-        }
+    for (int j0 = 0; j0 < NS; j0 += CH) {
+        if (LOAD) {
 #pragma unroll
-        for (int j = 0; j < NS; ++j) l[unit(j)] = v[j];
-    } else {
+            for (int j = 0; j < CH; ++j)
+                v[j] = __builtin_bit_cast(V, __builtin_nontemporal_load((const NV*)(st + toff + off(j0 + j))));
 #pragma unroll
-        for (int j = 0; j < NS; ++j) v[j] = l[unit(j)];
+            for (int j = 0; j < CH; ++j) l[unit(j0 + j)] = v[j];
+        } else {
 #pragma unroll
-        for (int j = 0; j < NS; ++j) {
-            long long so = 0;
+            for (int j = 0; j < CH; ++j) v[j] = l[unit(j0 + j)];
 #pragma unroll
-            for (int b = 0; b < LB; ++b)
-                if ((j >> b) & 1) so += hs[b];
-            __builtin_nontemporal_store(__builtin_bit_cast(NV, v[j]), (NV*)(st + toff + so));
+            for (int j = 0; j < CH; ++j)
+                __builtin_nontemporal_store(__builtin_bit_cast(NV, v[j]), (NV*)(st + toff + off(j0 + j)));
         }
     }
 }
 
-template <typename C, bool LOAD>
+template <typename C, bool LOAD, int NT = kThreads>
 __device__ __forceinline__ void move_tile(gptr<C> __restrict__ st, C* __restrict__ lds, const PassArgs& a,
                                           long long base)
 {
+    constexpr int LOGT = NT == 512 ? 9 : 8;
     const int tid = threadIdx.x;
     if constexpr (sizeof(C) == 8) {
         // complex64 pairs whenever qubit 0 is a tile qubit and a slice is full
-        if (a.L >= 1 && a.m > kLogThreads) {
-            const long long toff = base + local_off_bits(a, tid << 1, 1, kLogThreads + 1);
-            switch (a.m - kLogThreads - 1) {
-            case 0: move_tile_n<C, LOAD, 1, 2>(st, lds, a, toff); break;
-            case 1: move_tile_n<C, LOAD, 2, 2>(st, lds, a, toff); break;
-            case 2: move_tile_n<C, LOAD, 4, 2>(st, lds, a, toff); break;
-            case 3: move_tile_n<C, LOAD, 8, 2>(st, lds, a, toff); break;
-            default: move_tile_n<C, LOAD, 16, 2>(st, lds, a, toff); break;
+        if (a.L >= 1 && a.m > LOGT) {
+            const long long toff = base + local_off_bits(a, tid << 1, 1, LOGT + 1);
+            switch (a.m - LOGT - 1) {
+            case 0: move_tile_n<C, LOAD, 1, 2, NT>(st, lds, a, toff); break;
+            case 1: move_tile_n<C, LOAD, 2, 2, NT>(st, lds, a, toff); break;
+            case 2: move_tile_n<C, LOAD, 4, 2, NT>(st, lds, a, toff); break;
+            case 3: move_tile_n<C, LOAD, 8, 2, NT>(st, lds, a, toff); break;
+            default: move_tile_n<C, LOAD, 16, 2, NT>(st, lds, a, toff); break;
             }
             return;
         }
     }
-    const int lowb = a.m < kLogThreads ? a.m : kLogThreads;
+    const int lowb = a.m < LOGT ? a.m : LOGT;
     const long long toff = base + local_off_bits(a, tid, 0, lowb);
-    switch (a.m - kLogThreads) {
-    case 0: move_tile_n<C, LOAD, 1, 1>(st, lds, a, toff); break;
-    case 1: move_tile_n<C, LOAD, 2, 1>(st, lds, a, toff); break;
-    case 2: move_tile_n<C, LOAD, 4, 1>(st, lds, a, toff); break;
-    case 3: move_tile_n<C, LOAD, 8, 1>(st, lds, a, toff); break;
-    case 4: move_tile_n<C, LOAD, 16, 1>(st, lds, a, toff); break;
-    case 5: move_tile_n<C, LOAD, 32, 1>(st, lds, a, toff); break;
-    default:   // tiles smaller than one slice (whole states below 256 amplitudes)
+    switch (a.m - LOGT) {
+    case 0: move_tile_n<C, LOAD, 1, 1, NT>(st, lds, a, toff); break;
+    case 1: move_tile_n<C, LOAD, 2, 1, NT>(st, lds, a, toff); break;
+    case 2: move_tile_n<C, LOAD, 4, 1, NT>(st, lds, a, toff); break;
+    case 3: move_tile_n<C, LOAD, 8, 1, NT>(st, lds, a, toff); break;
+    case 4: move_tile_n<C, LOAD, 16, 1, NT>(st, lds, a, toff); break;
+    case 5: move_tile_n<C, LOAD, 32, 1, NT>(st, lds, a, toff); break;
+    default:   // tiles smaller than one slice (whole states below NT amplitudes)
         if (tid < (1 << a.m)) {
             if (LOAD) lds[tid] = st[toff];
             else st[toff] = lds[tid];
@@ -285,9 +289,11 @@ __device__ void op_dense_mfma(C* __restrict__ lds, int T, const DevOp& op, const
     }
     const int nblk = (T >> K) >> 4;
     const int bcol = group_base<K>(col, op);
-    // two blocks per iteration (blocks blk and blk + waves): their LDS reads are issued
-    // together and their accumulation chains interleave on the matrix pipe
-    constexpr int NW = NT / 64, U = 2;
+    // complex64: two blocks per iteration (blocks blk and blk + waves), their LDS reads
+    // issued together and their accumulation chains interleaved on the matrix pipe;
+    // complex128: one (the FP64 pipe gains nothing from it, and the registers it would
+    // take cost occupancy)
+    constexpr int NW = NT / 64, U = sizeof(C) == 8 ? 2 : 1;
     for (int blk = wave; blk < nblk; blk += U * NW) {
         int sb[U];
         bool live[U];
@@ -447,7 +453,7 @@ __device__ __forceinline__ void stage_operands(float* __restrict__ alds, cptr<fl
 }
 
 // One tile of one pass: HBM -> LDS, every op of the pass, LDS -> HBM.
-template <typename C, bool WIDE = true>
+template <typename C, bool WIDE = true, int NT = kThreads>
 __device__ __forceinline__ void run_tile(gptr<C> __restrict__ st, C* __restrict__ lds, const PassArgs& a,
                                          long long tile, cptr<DevOp> __restrict__ ops, cptr<C> __restrict__ pool,
                                          cptr<int> __restrict__ ipool, const float* __restrict__ alds,
@@ -456,22 +462,24 @@ __device__ __forceinline__ void run_tile(gptr<C> __restrict__ st, C* __restrict_
     const long long base = tile_base(a, tile);
     if (from_zero) {
         // the tile of |0...0> (Eq. 1): built on chip instead of read from HBM
-        for (int e = threadIdx.x; e < (1 << a.m); e += kThreads) {
+        for (int e = threadIdx.x; e < (1 << a.m); e += NT) {
             C z;
             z.x = (base == 0 && e == 0) ? 1 : 0;
             z.y = 0;
             lds[e] = z;
         }
     } else {
-        move_tile<C, true>(st, lds, a, base);
+        move_tile<C, true, NT>(st, lds, a, base);
     }
     __syncthreads();
-    apply_ops<C, WIDE>(lds, 1 << a.m, ops, a.op_begin, a.op_count, pool, ipool, alds, base);
-    move_tile<C, false>(st, lds, a, base);
+    apply_ops<C, WIDE, NT>(lds, 1 << a.m, ops, a.op_begin, a.op_count, pool, ipool, alds, base);
+    move_tile<C, false, NT>(st, lds, a, base);
 }
 
-template <typename C>
-__global__ __launch_bounds__(kThreads) void k_pass(C* __restrict__ st, C* __restrict__ st2, const PassArgs a,
+// WIDE = false: the variant without the register-heavy op paths, for passes free of
+// them (fewer registers, so more resident workgroups when LDS allows).
+template <typename C, bool WIDE, int NT>
+__global__ __launch_bounds__(NT) void k_pass(C* __restrict__ st, C* __restrict__ st2, const PassArgs a,
                                                    long long ntiles, int from_zero,
                                                    const DevOp* __restrict__ ops,
                                                    const C* __restrict__ pool,
@@ -485,13 +493,13 @@ __global__ __launch_bounds__(kThreads) void k_pass(C* __restrict__ st, C* __rest
     extern __shared__ __align__(16) unsigned char smem[];
     C* lds = reinterpret_cast<C*>(smem);
     float* alds = reinterpret_cast<float*>(smem + (sizeof(C) << a.m));
-    stage_operands(alds, (cptr<float>)apool, a);
+    stage_operands<NT>(alds, (cptr<float>)apool, a);
     __syncthreads();
     const long long total = st2 ? 2 * ntiles : ntiles;
     for (long long t = blockIdx.x; t < total; t += gridDim.x) {
         const bool second = t >= ntiles;
-        run_tile<C>((gptr<C>)(second ? st2 : st), lds, a, second ? t - ntiles : t, (cptr<DevOp>)ops, (cptr<C>)pool,
-                    (cptr<int>)ipool, alds, from_zero != 0);
+        run_tile<C, WIDE, NT>((gptr<C>)(second ? st2 : st), lds, a, second ? t - ntiles : t, (cptr<DevOp>)ops,
+                              (cptr<C>)pool, (cptr<int>)ipool, alds, from_zero != 0);
         __syncthreads();
     }
 }
@@ -1217,16 +1225,23 @@ static int device_cus()
 
 // Workgroups stride over the tiles (the hardware keeps as many resident as registers and
 // LDS allow; a finished workgroup's slot is refilled at once).
-template <typename R>
-hipError_t launch_pass_t(void* st, void* st2, const PassArgs& a, long long ntiles, const DevOp* ops,
-                         const void* pool, const int* ipool, const float* apool, hipStream_t s, bool from_zero)
+#ifndef QSV_PASS_THREADS_C64
+#define QSV_PASS_THREADS_C64 256
+#endif
+#ifndef QSV_PASS_THREADS_C128
+#define QSV_PASS_THREADS_C128 256
+#endif
+
+template <typename C, bool WIDE, int NT>
+hipError_t launch_pass_nt(void* st, void* st2, const PassArgs& a, long long ntiles, const DevOp* ops,
+                          const void* pool, const int* ipool, const float* apool, hipStream_t s, bool from_zero)
 {
-    using C = typename CT<R>::T;
     const long long total = st2 ? 2 * ntiles : ntiles;
     static bool attr_set = false;
     if (!attr_set) {
         // a 64 KiB complex128 tile plus its operand block exceeds the 64 KiB default
-        hipError_t e = hipFuncSetAttribute((const void*)k_pass<C>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
+        hipError_t e = hipFuncSetAttribute((const void*)k_pass<C, WIDE, NT>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
@@ -1235,9 +1250,21 @@ hipError_t launch_pass_t(void* st, void* st2, const PassArgs& a, long long ntile
     // once per workgroup rather than once per tile (measured on 2^18-tile passes: 6 %
     // faster for complex64, 10 % for complex128 than one workgroup per tile)
     const long long grid = std::min<long long>(total, 64ll * device_cus());
-    hipLaunchKernelGGL(k_pass<C>, dim3((unsigned)grid), dim3(kThreads), lds, s, (C*)st, (C*)st2, a, ntiles,
+    hipLaunchKernelGGL((k_pass<C, WIDE, NT>), dim3((unsigned)grid), dim3(NT), lds, s, (C*)st, (C*)st2, a, ntiles,
                        from_zero ? 1 : 0, ops, (const C*)pool, ipool, apool);
     return hipGetLastError();
+}
+
+template <typename R, bool WIDE>
+hipError_t launch_pass_t(void* st, void* st2, const PassArgs& a, long long ntiles, const DevOp* ops,
+                         const void* pool, const int* ipool, const float* apool, hipStream_t s, bool from_zero)
+{
+    using C = typename CT<R>::T;
+    // workgroup size: NT threads for full tiles, 256 for tiles smaller than NT amplitudes
+    constexpr int NTW = sizeof(C) == 8 ? QSV_PASS_THREADS_C64 : QSV_PASS_THREADS_C128;
+    if (NTW != kThreads && a.m >= (NTW == 512 ? 9 : 8) + (sizeof(C) == 8 ? 1 : 0))
+        return launch_pass_nt<C, WIDE, NTW>(st, st2, a, ntiles, ops, pool, ipool, apool, s, from_zero);
+    return launch_pass_nt<C, WIDE, kThreads>(st, st2, a, ntiles, ops, pool, ipool, apool, s, from_zero);
 }
 
 template <typename C, bool WIDE>
@@ -1269,10 +1296,13 @@ hipError_t launch_batch_pass(int dtype, const BatchItem* items, const int* count
 
 hipError_t launch_pass(int dtype, void* st, const PassArgs& a, long long ntiles, const DevOp* ops,
                        const void* pool, const int* ipool, const float* apool, hipStream_t s, void* st2,
-                       bool from_zero)
+                       bool from_zero, bool wide)
 {
-    return dtype == 0 ? launch_pass_t<float>(st, st2, a, ntiles, ops, pool, ipool, apool, s, from_zero)
-                      : launch_pass_t<double>(st, st2, a, ntiles, ops, pool, ipool, apool, s, from_zero);
+    if (dtype == 0)
+        return wide ? launch_pass_t<float, true>(st, st2, a, ntiles, ops, pool, ipool, apool, s, from_zero)
+                    : launch_pass_t<float, false>(st, st2, a, ntiles, ops, pool, ipool, apool, s, from_zero);
+    return wide ? launch_pass_t<double, true>(st, st2, a, ntiles, ops, pool, ipool, apool, s, from_zero)
+                : launch_pass_t<double, false>(st, st2, a, ntiles, ops, pool, ipool, apool, s, from_zero);
 }
 
 static hipError_t launch_fill16(void* st, long long bytes, uint4 first, uint4 rest, hipStream_t s)

@@ -141,10 +141,12 @@ hipError_t launch_batch_pass(int dtype, const BatchItem* items, const int* count
 hipError_t launch_zsum_batch(int dtype, const ZItem* items, const int* count, double* partial, int grid,
                              hipStream_t s);
 // st2 != nullptr applies the same pass to a second state of the same shape in the same
-// launch; from_zero makes the pass read |0...0> instead of the state buffers.
+// launch; from_zero makes the pass read |0...0> instead of the state buffers; wide = false
+// launches the variant without the register-heavy op paths (the pass must be free of
+// them: HostPlan::pwide).
 hipError_t launch_pass(int dtype, void* st, const PassArgs& a, long long ntiles, const DevOp* ops,
                        const void* pool, const int* ipool, const float* apool, hipStream_t s,
-                       void* st2 = nullptr, bool from_zero = false);
+                       void* st2 = nullptr, bool from_zero = false, bool wide = true);
 hipError_t launch_init_zero(int dtype, void* st, long long N, hipStream_t s);
 hipError_t launch_zero(int dtype, void* st, long long N, hipStream_t s);
 int norm_grid(long long N);
