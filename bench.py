@@ -79,6 +79,7 @@ def parse():
     ap.add_argument("--adjoint-batch", type=int, default=64)
     ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--plain-requests", type=int, default=256)
+    ap.add_argument("--capacity-requests", type=int, default=1024)
     ap.add_argument("--copy-probe", action="store_true",
                     help="copy 4 GiB device to device once before the timed steps (counter calibration)")
     return ap.parse_args()
@@ -313,14 +314,30 @@ def serving(args):
     auto = serve.run_batched(auto_reqs, circuits, sv)
     sv.close()
     torch.cuda.empty_cache()
+    # capacity: the same mixes with every request arriving at once (closed loop), on a
+    # prefix of the stream; circuits/s is then the sustainable maximum for the mix
+    kc = min(args.capacity_requests, len(reqs))
+    sv = serve.Server(max_slots=64, use_graph=True)
+    cap = serve.run_batched(reqs[:kc], circuits[:kc], sv, closed_loop=True)
+    sv.close()
+    torch.cuda.empty_cache()
+    sv = serve.Server(max_slots=64, use_graph=True, norm_guard=1e-5)
+    cap_auto = serve.run_batched(auto_reqs[:kc], circuits[:kc], sv, closed_loop=True)
+    sv.close()
+    torch.cuda.empty_cache()
     k = min(args.plain_requests, len(reqs))
     plain = serve.run_plain(reqs[:k], circuits[:k], fuse=False)
+    plain_fused = serve.run_plain(reqs[:k], circuits[:k], fuse=True)
     return {"workload": "%d requests, n~U{12..26}, brickwork depth~U{10..60}, 70%% complex64, Poisson 200/s, "
                         "seed 5" % len(reqs),
             "offered_per_s": 200.0, "input_generation_s": gen_s,
             "batched": batched,
             "batched_auto_precision": auto,
-            "plain": dict(plain, note="first %d requests of the same stream, one at a time, unfused" % k)}
+            "capacity": dict(cap, note="first %d requests of the same stream, all arriving at t = 0" % kc),
+            "capacity_auto_precision": dict(cap_auto, note="as capacity, precision chosen by Eq. 12"),
+            "plain": dict(plain, note="first %d requests of the same stream, one at a time, unfused" % k),
+            "plain_fused": dict(plain_fused, note="first %d requests of the same stream, one at a time, "
+                                                  "fused with the default plan options" % k)}
 
 
 def precision_study(args):

@@ -146,19 +146,27 @@ def _percentiles(lat: Sequence[float]) -> dict:
             "mean_ms": float(a.mean() * 1e3), "max_ms": float(a[-1] * 1e3)}
 
 
-def run_batched(requests, circuits, server: Server, time_limit_s: float = 600.0) -> dict:
+def run_batched(requests, circuits, server: Server, time_limit_s: float = 600.0, closed_loop: bool = False,
+                trace_every_s: float = 0.5) -> dict:
     """Open-loop continuous batching: submit each request at its arrival time, step the
-    server whenever it has work, record arrival -> result latency."""
+    server whenever it has work, record arrival -> result latency.  closed_loop: every
+    request arrives at time 0 (the server runs flat out; circuits/s is then its capacity
+    for this mix, and latency includes the time spent queued).  The queue is sampled
+    every trace_every_s: (time, requests submitted but not finished, running, waiting
+    for admission)."""
     N = len(requests)
+    arrival = [0.0 if closed_loop else r.arrival_s for r in requests]
     id2req: Dict[int, int] = {}
     lat = [None] * N
+    trace = []
+    next_trace = 0.0
     t0 = time.perf_counter()
     i = done = 0
     while done < N:
         now = time.perf_counter() - t0
         if now > time_limit_s:
             break
-        while i < N and requests[i].arrival_s <= now:
+        while i < N and arrival[i] <= now:
             r = requests[i]
             id2req[server.submit(r.n, r.dtype, circuits[i])] = i
             i += 1
@@ -166,18 +174,22 @@ def run_batched(requests, circuits, server: Server, time_limit_s: float = 600.0)
         tnow = time.perf_counter() - t0
         for res in server.results():
             k = id2req[res["id"]]
-            lat[k] = tnow - requests[k].arrival_s
+            lat[k] = tnow - arrival[k]
             done += 1
+        if tnow >= next_trace:
+            trace.append([round(tnow, 3), i - done, running, pending])
+            next_trace = tnow + trace_every_s
         if running == 0 and pending == 0 and i < N:
-            wait = requests[i].arrival_s - (time.perf_counter() - t0)
+            wait = arrival[i] - (time.perf_counter() - t0)
             if wait > 0:
                 time.sleep(min(wait, 0.01))
     wall = time.perf_counter() - t0
     got = [x for x in lat if x is not None]
     out = {"completed": len(got), "requests": N, "wall_s": wall,
-           "circuits_per_s": len(got) / wall if wall > 0 else None}
+           "circuits_per_s": len(got) / wall if wall > 0 else None, "closed_loop": closed_loop}
     out.update(_percentiles(got))
     out["server"] = server.stats()
+    out["queue_trace"] = {"columns": ["t_s", "in_system", "running", "waiting_admission"], "samples": trace}
     return out
 
 
