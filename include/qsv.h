@@ -202,6 +202,19 @@ qsv_status qsv_sync(qsv_state s);
  * with Neumaier's compensated sum in a fixed order (deterministic).  Synchronous. */
 qsv_status qsv_norm(qsv_state s, double* out);
 
+/* For callers that cannot allocate (code under stream or graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): qsv_norm on a raw device state, allocating
+ * nothing -- no device, pinned or host allocation, no library routine that allocates.
+ * amps: device pointer to 2^n_qubits amplitudes of `dtype`, 16-byte aligned (e.g. a torch
+ * tensor's data_ptr or the pointer qsv_info returns); n_qubits in [1, 34].  out_dev: device pointer to
+ * one double that receives sum_k |alpha_k|^2, bit-identical to qsv_norm's result.  The
+ * workgroup partials live in a fixed 16 KiB device array per GPU (its device address is
+ * looked up on the first call on each device and kept); every call on one device shares
+ * it, so calls that overlap on one device race -- order them on one stream.  Asynchronous
+ * on `stream` (hipStream_t, NULL = default stream): nothing is synchronised.  Errors:
+ * QSV_E_ARG (null or misaligned pointer, n_qubits out of range, bad dtype), QSV_E_DEVICE. */
+qsv_status qsv_norm_noalloc(const void* amps, int n_qubits, qsv_dtype dtype, double* out_dev, void* stream);
+
 /* One Pauli-sum term: coeff * prod_j sigma_{paulis[j]}(qubits[j]), paulis in "IXYZ",
  * n Pauli factors on distinct qubits.  qubits/paulis are host arrays. */
 typedef struct {

@@ -72,7 +72,7 @@ EXPORTS = [
     "qsv_set_state", "qsv_gate_matrix", "qsv_plan_create", "qsv_plan_free", "qsv_plan_get_stats",
     "qsv_plan_fused_gate", "qsv_plan_pass_info", "qsv_plan_pass_ops", "qsv_plan_emulate", "qsv_plan_apply",
     "qsv_plan_apply_range", "qsv_plan_apply_zero",
-    "qsv_apply_fused", "qsv_sync", "qsv_norm", "qsv_expval_pauli", "qsv_probs", "qsv_sample", "qsv_adjoint_grad",
+    "qsv_apply_fused", "qsv_sync", "qsv_norm", "qsv_norm_noalloc", "qsv_expval_pauli", "qsv_probs", "qsv_sample", "qsv_adjoint_grad",
     "qsv_dm_apply", "qsv_dm_probs", "qsv_dm_expval_pauli", "qsv_precision_select",
     "qsv_server_create", "qsv_server_free", "qsv_server_submit", "qsv_server_step", "qsv_server_results",
     "qsv_server_get_stats", "qsv_server_get_state", "qsv_server_release",
@@ -112,6 +112,7 @@ def lib():
     L.qsv_apply_fused.argtypes = [vp, ctypes.POINTER(Gate), sz, ctypes.POINTER(PlanOpts), ctypes.POINTER(PlanStats)]
     L.qsv_sync.argtypes = [vp]
     L.qsv_norm.argtypes = [vp, dp]
+    L.qsv_norm_noalloc.argtypes = [vp, i, i, vp, vp]
     L.qsv_expval_pauli.argtypes = [vp, ctypes.POINTER(PauliTerm), sz, dp, dp]
     L.qsv_probs.argtypes = [vp, ctypes.POINTER(i), i, vp, i]
     L.qsv_precision_select.argtypes = [i, sz, ctypes.c_double, ctypes.POINTER(i)]
@@ -445,6 +446,22 @@ class State:
             self.free()
         except Exception:
             pass
+
+
+def norm_noalloc(amps, out, stream=None) -> None:
+    """qsv_norm_noalloc: sum |alpha_k|^2 of the device tensor `amps` (complex64 or
+    complex128, 2^n elements) into the one-element float64 device tensor `out`, with no
+    allocation; asynchronous on `stream` (default: the current torch stream)."""
+    import torch
+    dt = {torch.complex64: "c64", torch.complex128: "c128"}[amps.dtype]
+    n = amps.numel().bit_length() - 1
+    if amps.numel() != (1 << n) or not amps.is_contiguous():
+        raise ValueError("amps must be a contiguous device tensor of 2^n elements")
+    if out.dtype != torch.float64 or out.numel() < 1 or out.device != amps.device:
+        raise ValueError("out must be a float64 device tensor on the state's device")
+    s = stream if stream is not None else torch.cuda.current_stream(amps.device)
+    check(lib().qsv_norm_noalloc(ctypes.c_void_p(amps.data_ptr()), n, _DT[dt], ctypes.c_void_p(out.data_ptr()),
+                                 ctypes.c_void_p(s.cuda_stream)))
 
 
 def simulate(n: int, ops, dtype: str = "c64", **opts) -> State:
