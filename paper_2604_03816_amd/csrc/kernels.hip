@@ -97,6 +97,21 @@ __device__ __forceinline__ long long local_off_bits(const PassArgs& a, int e, in
     return o;
 }
 
+// LDS position of tile element e.  The tile is stored XOR-swizzled so that the accesses
+// of an op on high tile qubits, whose lanes differ in address bits above the bank
+// period, spread over all banks: complex64 (8-byte elements) XORs element bits 1-4 with
+// bits 4-7 (bit 0 untouched, so the two elements of a 16-byte lane move stay adjacent),
+// complex128 (16 bytes) bits 0-3 with bits 3-6.  The map is a bijection on every range
+// [0, 2^m) and linear over XOR: for disjoint bit sets a | b = a ^ b, so
+// swz(a | b) = swz(a) ^ swz(b), which lets a uniform (scalar) part and a per-lane part be
+// swizzled separately and combined with one XOR.
+template <typename C>
+__device__ __forceinline__ int swz(int e)
+{
+    if constexpr (sizeof(C) == 8) return e ^ (((e >> 4) & 15) << 1);
+    else return e ^ ((e >> 3) & 15);
+}
+
 // Move a tile between HBM and LDS.  Every lane moves 16 bytes at a time: W = 1
 // complex128 or W = 2 adjacent complex64 amplitudes (local bit 0 is qubit 0, so such a
 // pair is contiguous in HBM).  Local index e = W (256 * slice + tid) + w: the bits from
@@ -130,8 +145,12 @@ __device__ __forceinline__ void move_tile_n(gptr<C> __restrict__ st, C* __restri
     constexpr int CH = NS < 8 ? NS : 8;
     V v[CH];
     V* l = reinterpret_cast<V*>(lds);
-    // 16-byte unit u = NT j + tid holds tile elements W u .. W u + W - 1
-    auto unit = [&](int j) { return (j << LOGT) + tid; };
+    // 16-byte unit u = NT j + tid holds tile elements W u .. W u + W - 1, stored at the
+    // swizzled position of element W u (the swizzle keeps the pair together).  The
+    // swizzle reads element bits below 8 only, which come from tid, and leaves the bits
+    // from j alone, so the position is NT j + swz(W tid) / W: an immediate offset per j.
+    const int ut = swz<C>(W * tid) / W;
+    auto unit = [&](int j) { return (j << LOGT) + ut; };
     auto off = [&](int j) {
         long long so = 0;
 #pragma unroll
@@ -188,8 +207,8 @@ __device__ __forceinline__ void move_tile(gptr<C> __restrict__ st, C* __restrict
     case 5: move_tile_n<C, LOAD, 32, 1, NT>(st, lds, a, toff); break;
     default:   // tiles smaller than one slice (whole states below NT amplitudes)
         if (tid < (1 << a.m)) {
-            if (LOAD) lds[tid] = st[toff];
-            else st[toff] = lds[tid];
+            if (LOAD) lds[swz<C>(tid)] = st[toff];
+            else st[toff] = lds[swz<C>(tid)];
         }
         break;
     }
@@ -227,14 +246,15 @@ __device__ void op_dense(C* __restrict__ lds, int T, const DevOp& op, cptr<C> __
 {
     constexpr int D = 1 << K;
     const int G = T >> K;
-    const int bt = group_base<K>(threadIdx.x, op);
+    // LDS position of row r of group g0 + tid: swz(group_base(g0)) (uniform, scalar work)
+    // ^ swz(group_base(tid)) ^ swz(row_off(r)) (per lane and per op)
+    const int bt = swz<C>(group_base<K>(threadIdx.x, op));
     for (int g0 = 0; g0 < G; g0 += NT) {
         if (g0 + (int)threadIdx.x >= G) break;
-        // b = group_base(g0) | group_base(tid): the uniform part is scalar work
-        const int b = group_base<K>(g0, op) | bt;
+        const int b = __builtin_amdgcn_readfirstlane(swz<C>(group_base<K>(g0, op))) ^ bt;
         C v[D];
 #pragma unroll
-        for (int r = 0; r < D; ++r) v[r] = lds[b | row_off<K>(r, op)];
+        for (int r = 0; r < D; ++r) v[r] = lds[b ^ swz<C>(row_off<K>(r, op))];
         // rows are not unrolled for wide gates: the row's matrix entries are uniform
         // (scalar) loads, the inputs stay in registers
         constexpr int RU = K <= 2 ? D : 1;
@@ -244,7 +264,7 @@ __device__ void op_dense(C* __restrict__ lds, int T, const DevOp& op, cptr<C> __
             acc.x = acc.y = 0;
 #pragma unroll
             for (int c = 0; c < D; ++c) cmac(acc, M[r * D + c], v[c]);
-            lds[b | row_off<K>(r, op)] = acc;
+            lds[b ^ swz<C>(row_off<K>(r, op))] = acc;
         }
     }
 }
@@ -279,16 +299,17 @@ __device__ void op_dense_mfma(C* __restrict__ lds, int T, const DevOp& op, const
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) a[rb][ks] = A[(rb * KS + ks) * 64 + lane];
     // this lane's row offsets (the same for every block)
+    // (swizzled LDS positions: the lane's group and row parts are folded into rin / rout)
+    const int bcol = swz<C>(group_base<K>(col, op));
     int rin[KS / 2], rout[2 * RB];
 #pragma unroll
-    for (int j = 0; j < KS / 2; ++j) rin[j] = row_off<K>(4 * j + q, op);
+    for (int j = 0; j < KS / 2; ++j) rin[j] = swz<C>(row_off<K>(4 * j + q, op)) ^ bcol;
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
-        rout[2 * rb] = row_off<K>(8 * rb + 2 * q, op);
-        rout[2 * rb + 1] = row_off<K>(8 * rb + 2 * q + 1, op);
+        rout[2 * rb] = swz<C>(row_off<K>(8 * rb + 2 * q, op)) ^ bcol;
+        rout[2 * rb + 1] = swz<C>(row_off<K>(8 * rb + 2 * q + 1, op)) ^ bcol;
     }
     const int nblk = (T >> K) >> 4;
-    const int bcol = group_base<K>(col, op);
     // complex64: two blocks per iteration (blocks blk and blk + waves), their LDS reads
     // issued together and their accumulation chains interleaved on the matrix pipe;
     // complex128: one (the FP64 pipe gains nothing from it, and the registers it would
@@ -303,13 +324,13 @@ __device__ void op_dense_mfma(C* __restrict__ lds, int T, const DevOp& op, const
             live[u] = b < nblk;   // uniform
             // the block's part of the group base is uniform (scalar unit); the lane's
             // part was computed once
-            sb[u] = __builtin_amdgcn_readfirstlane(group_base<K>((live[u] ? b : blk) << 4, op)) | bcol;
+            sb[u] = __builtin_amdgcn_readfirstlane(swz<C>(group_base<K>((live[u] ? b : blk) << 4, op)));
         }
         C v[U][KS / 2];
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int j = 0; j < KS / 2; ++j) v[u][j] = lds[sb[u] | rin[j]];
+            for (int j = 0; j < KS / 2; ++j) v[u][j] = lds[sb[u] ^ rin[j]];
         Acc acc[U][RB];
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -341,8 +362,8 @@ __device__ void op_dense_mfma(C* __restrict__ lds, int T, const DevOp& op, const
                 o0.y = acc[u][rb][1];
                 o1.x = acc[u][rb][2];
                 o1.y = acc[u][rb][3];
-                lds[sb[u] | rout[2 * rb]] = o0;
-                lds[sb[u] | rout[2 * rb + 1]] = o1;
+                lds[sb[u] ^ rout[2 * rb]] = o0;
+                lds[sb[u] ^ rout[2 * rb + 1]] = o1;
             }
         }
     }
@@ -355,15 +376,15 @@ __device__ void op_perm(C* __restrict__ lds, int T, const DevOp& op, cptr<C> __r
     constexpr int D = 1 << K;
     const int G = T >> K;
     const bool phased = op.flags != 0;
-    const int bt = group_base<K>(threadIdx.x, op);
+    const int bt = swz<C>(group_base<K>(threadIdx.x, op));
     for (int g0 = 0; g0 < G; g0 += NT) {
         if (g0 + (int)threadIdx.x >= G) break;
-        const int b = group_base<K>(g0, op) | bt;
+        const int b = __builtin_amdgcn_readfirstlane(swz<C>(group_base<K>(g0, op))) ^ bt;
         C v[D];
 #pragma unroll
-        for (int r = 0; r < D; ++r) v[r] = lds[b | row_off<K>(src[r], op)];
+        for (int r = 0; r < D; ++r) v[r] = lds[b ^ swz<C>(row_off<K>(src[r], op))];
 #pragma unroll
-        for (int r = 0; r < D; ++r) lds[b | row_off<K>(r, op)] = phased ? cmul(ph[r], v[r]) : v[r];
+        for (int r = 0; r < D; ++r) lds[b ^ swz<C>(row_off<K>(r, op))] = phased ? cmul(ph[r], v[r]) : v[r];
     }
 }
 
@@ -380,12 +401,14 @@ __device__ __forceinline__ void op_diag(C* __restrict__ lds, int T, const DevOp&
         lp[j] = (j < op.k) ? op.lpos[j] : -1;
         if (j < op.k && lp[j] < 0) gfix |= (int)((base >> op.gbit[j]) & 1) << j;
     }
+    const int st = swz<C>(threadIdx.x);
     for (int e = threadIdx.x; e < T; e += NT) {
         int idx = gfix;
 #pragma unroll
         for (int j = 0; j < kMaxDiagK; ++j)
             if (lp[j] >= 0) idx |= ((e >> lp[j]) & 1) << j;
-        lds[e] = cmul(lds[e], Dg[idx]);
+        const int pe = swz<C>(e - (int)threadIdx.x) ^ st;   // e - tid: a multiple of NT
+        lds[pe] = cmul(lds[pe], Dg[idx]);
     }
 }
 
@@ -461,7 +484,8 @@ __device__ __forceinline__ void run_tile(gptr<C> __restrict__ st, C* __restrict_
 {
     const long long base = tile_base(a, tile);
     if (from_zero) {
-        // the tile of |0...0> (Eq. 1): built on chip instead of read from HBM
+        // the tile of |0...0> (Eq. 1): built on chip instead of read from HBM (element 0
+        // keeps position 0 under the swizzle and every other element is zero)
         for (int e = threadIdx.x; e < (1 << a.m); e += NT) {
             C z;
             z.x = (base == 0 && e == 0) ? 1 : 0;
