@@ -127,6 +127,10 @@ typedef struct {
                             fusion may merge them across one another and a pass may take
                             such an op ahead of deferred ones; -1: the per-qubit DAG of
                             Section 5.1 exactly */
+    double op_cost;      /* on-chip cost of one op beyond its arithmetic, in FMA per
+                            amplitude (its LDS round trip and barrier), charged by the
+                            cost-aware fusion (Eq. 13 trade-off) and by the pass budget;
+                            0 = default, > 0 otherwise */
 } qsv_plan_opts;
 
 typedef struct {

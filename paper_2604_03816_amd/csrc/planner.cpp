@@ -83,6 +83,8 @@ bool plan_opts_from(int dtype, const qsv_plan_opts* pub, PlanOpts& o, std::strin
         }
         o.mfma_min_k = pub->matrix_cores < 0 ? 0 : pub->matrix_cores;
     }
+    if (pub->op_cost < 0) { err = "op_cost must be >= 0"; return false; }
+    if (pub->op_cost > 0) o.sigma = pub->op_cost;
     if (pub->commute < -1 || pub->commute > 1) { err = "commute must be 0, 1 or -1"; return false; }
     if (pub->commute) o.commute = pub->commute > 0;
     if (o.fuse != 1) o.commute = 0;

@@ -39,7 +39,8 @@ class Gate(ctypes.Structure):
 class PlanOpts(ctypes.Structure):
     _fields_ = [("fuse", ctypes.c_int), ("kmax", ctypes.c_int), ("cost_aware", ctypes.c_int),
                 ("tile_qubits", ctypes.c_int), ("low_qubits", ctypes.c_int),
-                ("pass_budget", ctypes.c_double), ("matrix_cores", ctypes.c_int), ("commute", ctypes.c_int)]
+                ("pass_budget", ctypes.c_double), ("matrix_cores", ctypes.c_int), ("commute", ctypes.c_int),
+                ("op_cost", ctypes.c_double)]
 
 
 class PlanStats(ctypes.Structure):
@@ -234,7 +235,7 @@ class ArrayGateList:
 
 
 def _opts(fuse=True, kmax=0, cost_aware=0, tile_qubits=0, low_qubits=0, pass_budget=0.0,
-          matrix_cores=0, commute=0) -> PlanOpts:
+          matrix_cores=0, commute=0, op_cost=0.0) -> PlanOpts:
     """fuse: True/1 DAG fusion, False/0 plain (one gate per pass), 2 = no fusion but
     gates share passes; matrix_cores: dense ops on >= this many targets use MFMA
     (0 default, -1 never); commute: commutation-aware DAG (0/1 default on, -1 off or
@@ -248,6 +249,7 @@ def _opts(fuse=True, kmax=0, cost_aware=0, tile_qubits=0, low_qubits=0, pass_bud
     o.tile_qubits = tile_qubits
     o.low_qubits = low_qubits
     o.pass_budget = pass_budget
+    o.op_cost = op_cost
     return o
 
 

@@ -78,6 +78,27 @@ def test_argument_errors():
         qsv.Plan(16, "c64", C.ghz(16), kmax=6)
     with pytest.raises(qsv.QSVError):
         qsv.Plan(16, "c64", C.ghz(16), commute=2)
+    with pytest.raises(qsv.QSVError):
+        qsv.Plan(16, "c64", C.ghz(16), op_cost=-1.0)
+
+
+def test_op_cost_trades_fused_ops_for_arithmetic():
+    """The per-op cost charged by the cost-aware fusion (Eq. 13 trade-off): a large one
+    merges far more than a small one, and every resulting plan stays exact (oracle replay
+    of the fused list equals the circuit)."""
+    n = 10
+    ops = C.brickwork(n, 12, seed=11)
+    ref = oracle.simulate(n, ops)
+    counts = {}
+    for oc in (4.0, 8.0, 24.0, 64.0):
+        p = qsv.Plan(n, "c128", ops, op_cost=oc, tile_qubits=8)
+        counts[oc] = p.stats()["fused_out"]
+        psi = oracle.zero_state(n)
+        for t, m, d in p.fused_gates():
+            oracle.apply(psi, m, t)
+        assert oracle.max_abs_diff(ref, psi) <= 1e-12
+        p.free()
+    assert counts[64.0] < counts[8.0] < counts[4.0]
 
 
 def test_null_arguments_return_errors():
