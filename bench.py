@@ -649,6 +649,14 @@ def noise_bench(args):
     return out
 
 
+def progress(msg):
+    """A progress line on stderr (the result line alone goes to stdout)."""
+    print("[bench %.0fs] %s" % (time.perf_counter() - _T0, msg), file=sys.stderr, flush=True)
+
+
+_T0 = time.perf_counter()
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -665,7 +673,9 @@ def main():
     probe = copy_probe(torch) if args.copy_probe else None
     ops = C.brickwork(n, args.depth, args.seed)
     terms = C.zz_chain_terms(n)
+    progress("start")
     main_rec = run_dtype(torch, qsv, C, args, "c64", ops, terms)
+    progress("complex64 step done")
     rec = {
         "metric": "fused-gate amplitude GB/s (% HBM peak) at 30q",
         "value": main_rec["value"],
@@ -691,28 +701,38 @@ def main():
         rec["copy_probe"] = probe
     if not args.no_c128:
         r = run_dtype(torch, qsv, C, args, "c128", ops, terms)
+        progress("complex128 step done")
         rec["c128"] = {"value": r["value"], "unit": "GB/s", "dtype": "f64", "ms_per_step": r["ms_per_step"],
                        "fused_gates": r["fused_gates"], "passes": r["passes"], "avg_pass_ms": r["avg_pass_ms"],
                        "roofline": r["roofline"], "hbm": r["hbm"], "alu": r["alu"],
                        "norm_minus_1": r["norm_minus_1"]}
     if not args.no_serve:
         rec["serving"] = serving(args)
+        progress("serving done")
     if not args.no_precision:
         rec["precision"] = precision_study(args)
+        progress("precision done")
     if not args.no_adjoint:
         rec["adjoint"] = adjoint_bench(args)
+        progress("adjoint done")
     if not args.no_sampling:
         rec["sampling"] = sampling_bench(args, ops)
+        progress("sampling done")
     if not args.no_noise:
         rec["noise"] = noise_bench(args)
+        progress("noise done")
     if not args.no_commute:
         rec["commutation"] = commutation_bench(args)
+        progress("commutation done")
     if not args.no_fusion:
         rec["fusion"] = fusion_bench(args)
+        progress("fusion done")
     if args.kernel_sweep:
         rec["kernel_sweep"] = kernel_sweep(args)
+        progress("kernel_sweep done")
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(C, args, ops)
+        progress("cpu_baseline done")
     print(json.dumps(rec))
 
 

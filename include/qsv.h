@@ -118,10 +118,10 @@ typedef struct {
     int low_qubits;      /* contiguous low qubits kept in every tile, 0 = default */
     double pass_budget;  /* per-pass arithmetic budget (FMA per amplitude), 0 = default,
                             < 0 = unlimited */
-    int matrix_cores;    /* dense ops on >= this many targets run on matrix cores (MFMA;
-                            FP32 for complex64, FP64 for complex128) when their operand
-                            block fits the pass's LDS budget: 0 = default (3), -1 = never;
-                            in [3, 5] otherwise */
+    int matrix_cores;    /* dense ops on >= this many (and at most 4) targets run on matrix
+                            cores (MFMA; FP32 for complex64, FP64 for complex128) when their
+                            operand block fits the pass's LDS budget: 0 = default (3),
+                            -1 = never, 3 or 4 otherwise */
     int commute;         /* fuse = 1 only.  1 (default): commutation-aware DAG -- ops that
                             are diagonal on every qubit they share are left unordered, so
                             fusion may merge them across one another and a pass may take

@@ -434,9 +434,9 @@ __device__ __forceinline__ void apply_ops(C* __restrict__ lds, int T, cptr<DevOp
         const DevOp op = ops[op_begin + oi];
         cptr<C> M = pool + op.off;
         if (op.kind == OP_DENSE && op.aoff >= 0) {
-            // the planner gives matrix cores 3- and 4-qubit ops only
+            // the planner gives matrix cores 3- and 4-qubit ops only (kMaxMfmaK)
             if (op.k == 3) op_dense_mfma<C, 3, NT>(lds, T, op, alds + op.aoff);
-            else op_dense_mfma<C, 4, NT>(lds, T, op, alds + op.aoff);
+            else if (op.k == 4) op_dense_mfma<C, 4, NT>(lds, T, op, alds + op.aoff);
             lds_sync();
             continue;
         }

@@ -77,8 +77,8 @@ bool plan_opts_from(int dtype, const qsv_plan_opts* pub, PlanOpts& o, std::strin
     if (pub->low_qubits) o.low_qubits = pub->low_qubits;
     if (pub->pass_budget != 0) o.pass_budget = pub->pass_budget;
     if (pub->matrix_cores) {
-        if (pub->matrix_cores != -1 && (pub->matrix_cores < 3 || pub->matrix_cores > kMaxK)) {
-            err = "matrix_cores must be 0, -1 or in [3, 5]";
+        if (pub->matrix_cores != -1 && (pub->matrix_cores < 3 || pub->matrix_cores > kMaxMfmaK)) {
+            err = "matrix_cores must be 0, -1, 3 or 4 (matrix-core ops have 3 or 4 targets)";
             return false;
         }
         o.mfma_min_k = pub->matrix_cores < 0 ? 0 : pub->matrix_cores;
@@ -152,7 +152,8 @@ double op_fma(const FGate& g)
 double op_cost(const FGate& g, const PlanOpts& o)
 {
     const double f = op_fma(g);
-    if (g.kind == OP_DENSE && o.fp32_mfma && o.mfma_min_k > 0 && g.k >= o.mfma_min_k) return 0.5 * f;
+    if (g.kind == OP_DENSE && o.fp32_mfma && o.mfma_min_k > 0 && g.k >= o.mfma_min_k && g.k <= kMaxMfmaK)
+        return 0.5 * f;
     return f;
 }
 
@@ -846,7 +847,7 @@ bool make_plan(int n, int dtype, const std::vector<InGate>& gates, const PlanOpt
                 const int per = dtype == 0 ? 1 : 2;
                 const int af = per * (4 << (2 * g.k));
                 const int at = (a.a_len + 3) & ~3;
-                if (o.mfma_min_k > 0 && g.k >= o.mfma_min_k && (1 << (a.m - g.k)) >= 16 &&
+                if (o.mfma_min_k > 0 && g.k >= o.mfma_min_k && g.k <= kMaxMfmaK && (1 << (a.m - g.k)) >= 16 &&
                     at + af <= o.mfma_lds_floats) {
                     const std::vector<double> A = mfma_operand(g.m, g.k, dtype != 0);
                     P.apool.resize((size_t)a.a_off + at, 0.0f);

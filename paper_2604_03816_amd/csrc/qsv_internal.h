@@ -7,6 +7,7 @@
 namespace qsv {
 
 constexpr int kMaxK = 5;            // widest fused gate (dense / permutation)
+constexpr int kMaxMfmaK = 4;        // widest dense op the matrix-core path takes
 constexpr int kMaxDiagK = 5;        // widest diagonal op
 constexpr int kThreads = 256;       // threads per tile workgroup
 constexpr int kLogThreads = 8;

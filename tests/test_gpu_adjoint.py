@@ -38,6 +38,29 @@ def test_hea_tfim_12q_matches_parameter_shift(qsv, dtype):
         assert rel(G[b], g_ref) <= REL[dtype], rel(G[b], g_ref)
 
 
+def test_24q_complex64_against_complex128_and_finite_differences(qsv):
+    """At the gradient workload's size (24 qubits, 8 layers, 384 parameters, TFIM):
+    complex64 gradients within 1e-3 relative error of complex128 ones, and complex128
+    against central differences (h = 1e-6, FP64 energies) on a few parameters."""
+    n, layers = 24, 8
+    tpl = C.hea(n, layers, ring=True)
+    terms = C.tfim_terms(n)
+    params = C.hea_params(n, layers, seed=6, batch=2)
+    E128, G128 = qsv.adjoint_grad(n, tpl, params, terms, "c128")
+    E64, G64 = qsv.adjoint_grad(n, tpl, params, terms, "c64")
+    for b in range(2):
+        assert rel(G64[b], G128[b]) <= REL["c64"], rel(G64[b], G128[b])
+        assert abs(E64[b] - E128[b]) <= 1e-4 * max(1.0, abs(E128[b]))
+    h = 1e-6
+    for j in (0, 191, 383):
+        p = params[0].copy()
+        p[j] += h
+        ep, _ = qsv.adjoint_grad(n, tpl, p, terms, "c128")
+        p[j] -= 2 * h
+        em, _ = qsv.adjoint_grad(n, tpl, p, terms, "c128")
+        assert abs(G128[0][j] - (ep - em) / (2 * h)) <= 1e-7
+
+
 def test_finite_differences_small_circuit(qsv):
     """Central differences at h = 1e-6 in FP64 (truncation O(h^2), rounding ~1e-10)."""
     n, layers = 6, 3

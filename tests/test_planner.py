@@ -80,6 +80,8 @@ def test_argument_errors():
         qsv.Plan(16, "c64", C.ghz(16), commute=2)
     with pytest.raises(qsv.QSVError):
         qsv.Plan(16, "c64", C.ghz(16), op_cost=-1.0)
+    with pytest.raises(qsv.QSVError):   # matrix-core ops have 3 or 4 targets
+        qsv.Plan(16, "c64", C.ghz(16), matrix_cores=5)
 
 
 def test_op_cost_trades_fused_ops_for_arithmetic():
@@ -272,7 +274,7 @@ def test_fusion_modes_and_matrix_core_option():
     m128 = qsv.Plan(n, "c128", ops).stats()
     assert m128["mfma_ops"] > 0
     assert qsv.Plan(n, "c128", ops, matrix_cores=-1).stats()["fused_out"] == m128["fused_out"]
-    for bad in ({"fuse": 3}, {"fuse": -1}, {"matrix_cores": 2}, {"matrix_cores": 6}, {"matrix_cores": -2}):
+    for bad in ({"fuse": 3}, {"fuse": -1}, {"matrix_cores": 2}, {"matrix_cores": 5}, {"matrix_cores": 6}, {"matrix_cores": -2}):
         with pytest.raises(qsv.QSVError):
             qsv.Plan(n, "c64", ops, **bad)
 
@@ -294,7 +296,7 @@ def test_device_tables_reproduce_the_circuit(seed, tq, lq):
     psi0 = np.ascontiguousarray(v / np.linalg.norm(v))
     ref = oracle.simulate(n, ops, psi=psi0.copy())
     for opts in ({}, {"fuse": False}, {"fuse": 2}, {"cost_aware": -1}, {"kmax": 1}, {"pass_budget": -1},
-                 {"matrix_cores": -1}, {"matrix_cores": 5}):
+                 {"matrix_cores": -1}, {"matrix_cores": 4}):
         dt = "c64" if (seed % 2 or tq == 13) else "c128"   # 13-qubit tiles fit LDS only in complex64
         plan = qsv.Plan(n, dt, ops, tile_qubits=tq, low_qubits=lq, **opts)
         got = plan.emulate(psi0)
