@@ -343,7 +343,8 @@ def serving(args):
 def precision_study(args):
     """Hardware-efficient ansatz (6 layers of RY, RZ on every qubit + CZ ladder, angles
     from seed 4) at 30 and 32 qubits: <sum Z_i Z_i+1> and <sum X_i> in complex64 and
-    complex128, their difference and the complex64 state's fidelity against complex128."""
+    complex128, their difference, and the complex64 state against the complex128 one over
+    the whole state (max |d alpha|, raw and normalised infidelity)."""
     import torch
     from paper_2604_03816_amd import circuits as C
     from paper_2604_03816_amd import qsv
@@ -374,7 +375,7 @@ def precision_study(args):
                               "d_x": abs(rec["c64"]["x"] - rec["c128"]["x"]), **gap}
         for st in states.values():
             st.free()
-        del a, b, states
+        del states
         torch.cuda.empty_cache()
         out.append(rec)
     return out
