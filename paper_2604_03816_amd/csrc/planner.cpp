@@ -53,6 +53,9 @@ PlanOpts default_opts(int dtype)
         o.sigma = 8;
         o.mfma_min_k = 3;
         o.fp32_mfma = true;
+        o.mfma_lds_floats = 4096;  // 16 KiB: room for every 3- and 4-qubit op of a pass on
+                                   // matrix cores (a VALU 4-qubit op costs more than the
+                                   // workgroup the larger block can cost in occupancy)
     } else {            // complex128: 16-byte amplitudes
         o.tile_qubits = 12;
         o.low_qubits = 3;   // 8 contiguous amplitudes: 128-byte runs, as complex64's 16
