@@ -328,6 +328,10 @@ def serving(args):
     k = min(args.plain_requests, len(reqs))
     plain = serve.run_plain(reqs[:k], circuits[:k], fuse=False)
     plain_fused = serve.run_plain(reqs[:k], circuits[:k], fuse=True)
+    # the same prefix fused one at a time with every request arriving at once: the plain
+    # path's capacity, to set beside the batched capacity
+    plain_fused_cap = serve.run_plain([dataclasses.replace(r, arrival_s=0.0) for r in reqs[:k]], circuits[:k],
+                                      fuse=True)
     return {"workload": "%d requests, n~U{12..26}, brickwork depth~U{10..60}, 70%% complex64, Poisson 200/s, "
                         "seed 5" % len(reqs),
             "offered_per_s": 200.0, "input_generation_s": gen_s,
@@ -337,7 +341,8 @@ def serving(args):
             "capacity_auto_precision": dict(cap_auto, note="as capacity, precision chosen by Eq. 12"),
             "plain": dict(plain, note="first %d requests of the same stream, one at a time, unfused" % k),
             "plain_fused": dict(plain_fused, note="first %d requests of the same stream, one at a time, "
-                                                  "fused with the default plan options" % k)}
+                                                  "fused with the default plan options" % k),
+            "plain_fused_capacity": dict(plain_fused_cap, note="as plain_fused, all arriving at t = 0")}
 
 
 def precision_study(args):
