@@ -699,6 +699,46 @@ PassPlan build_pass(int n, const std::vector<FGate>& fused, const std::vector<ch
     return pp;
 }
 
+// Diagonal ops on disjoint qubits share no DAG edge, so fusion leaves them apart, yet
+// they commute and their product is again diagonal, costing one complex multiply per
+// amplitude like each of them (a layer of single-qubit phase rotations would otherwise
+// cost one on-chip round trip per qubit).  Walking the fused list in order, a diagonal
+// op moves back past every op it commutes with to the nearest earlier diagonal op whose
+// union with it stays within the width bound, and the two become one.  Moving it back
+// is exact: it commutes with every op it passes.
+void merge_diagonals(std::vector<FGate>& ops, int kmax)
+{
+    constexpr int kWindow = 64;   // earlier ops examined per diagonal op
+    std::vector<FGate> out;
+    out.reserve(ops.size());
+    for (FGate& v : ops) {
+        if (v.kind == OP_DIAG) {
+            const unsigned long long qv = qubit_mask(v);
+            int hit = -1;
+            for (int t = (int)out.size() - 1, seen = 0; t >= 0 && seen < kWindow; --t, ++seen) {
+                const FGate& u = out[(size_t)t];
+                if (u.kind == OP_DIAG && __builtin_popcountll(qubit_mask(u) | qv) <= kmax) {
+                    hit = t;
+                    break;
+                }
+                if (!ops_commute(u, v)) break;
+            }
+            if (hit >= 0) {
+                bool ok = false;
+                FGate f = fuse_pair(out[(size_t)hit], v, kmax, ok);
+                if (ok && f.kind == OP_DIAG) {
+                    out[(size_t)hit] = std::move(f);
+                    continue;
+                }
+            }
+        }
+        out.push_back(std::move(v));
+    }
+    ops.clear();
+    for (FGate& g : out)
+        if (!is_identity(g)) ops.push_back(std::move(g));
+}
+
 // Pass scheduling.  Each pass is the best of several greedy candidates: the tile that
 // grows with the ops in their order, and tiles fixed in advance to the low L qubits
 // plus m - L consecutive others (every window position).  The fixed windows follow the
@@ -781,6 +821,7 @@ bool make_plan(int n, int dtype, const std::vector<InGate>& gates, const PlanOpt
         if (o.fuse == 1 && o.commute) in = fuse_commuting(in, n, o, true);
         for (FGate& g : in)
             if (!is_identity(g)) P.fused.push_back(std::move(g));
+        if (o.fuse == 1 && o.commute) merge_diagonals(P.fused, o.kmax);
     }
     if (!schedule_passes(n, P.fused, o, P.passes, err)) return false;
     if (o.fuse == 1 && o.commute) {
@@ -790,6 +831,7 @@ bool make_plan(int n, int dtype, const std::vector<InGate>& gates, const PlanOpt
         std::vector<FGate> alt;
         for (FGate& g : fuse_commuting(in, n, o, false))
             if (!is_identity(g)) alt.push_back(std::move(g));
+        merge_diagonals(alt, o.kmax);
         std::vector<PassPlan> alt_passes;
         if (!schedule_passes(n, alt, o, alt_passes, err)) return false;
         auto arith = [&](const std::vector<FGate>& f) {

@@ -224,6 +224,26 @@ def test_diagonal_gates_merge_and_need_no_tile_capacity():
     assert np.max(np.abs(plan_replay(n, plan) - ref)) < 1e-12
 
 
+def test_disjoint_diagonal_ops_merge_across_commuting_ops_only():
+    """Diagonal ops on disjoint qubits have no DAG edge; with the commutation-aware DAG
+    (the default) a diagonal op still joins the nearest earlier diagonal op within the
+    width bound, moving back only past ops it commutes with.  The per-qubit DAG of
+    Section 5.1 (commute = -1) keeps them apart."""
+    n = 6
+    layer = [C.Op("RZ", (q,), (0.3 + 0.1 * q,)) for q in range(n)]
+    on = qsv.Plan(n, "c128", layer).stats()
+    assert on["fused_out"] == on["diag_ops"] == 2          # 5 + 1 targets
+    assert qsv.Plan(n, "c128", layer, commute=-1).stats()["fused_out"] == n
+    assert qsv.Plan(n, "c128", layer, kmax=2).stats()["fused_out"] == 3
+    # TOFFOLI(1, 2; 3) is diagonal on its controls: RZ on a control or on a free qubit
+    # passes it and joins RZ(0); RZ on its target does not
+    for q2, merged in ((3, False), (1, True), (4, True)):
+        ops = [C.Op("RZ", (0,), (0.7,)), C.Op("TOFFOLI", (1, 2, 3)), C.Op("RZ", (q2,), (0.4,))]
+        plan = qsv.Plan(n, "c128", ops, kmax=2)
+        assert plan.stats()["fused_out"] == (2 if merged else 3), q2
+        assert np.max(np.abs(plan_replay(n, plan) - oracle.simulate(n, ops))) < 1e-13
+
+
 def test_identity_products_are_dropped():
     ops = [C.Op("X", (3,)), C.Op("X", (3,)), C.Op("CNOT", (0, 1)), C.Op("CNOT", (0, 1))]
     plan = qsv.Plan(5, "c64", ops)
