@@ -154,6 +154,24 @@ qsv_status qsv_plan_create(int n_qubits, qsv_dtype dtype, const qsv_gate* gates,
 qsv_status qsv_plan_free(qsv_plan p);
 qsv_status qsv_plan_get_stats(qsv_plan p, qsv_plan_stats* st);
 
+/* Re-fills plan p with new matrices for the same circuit shape (n_gates equal to the
+ * plan's gate count; gate by gate the same k and targets), keeping its fusion and its
+ * passes: each fused matrix becomes the Eq. 9 product of its members' new matrices, in
+ * the plan's order.  For circuits whose structure is fixed while parameters change
+ * (variational loops): planning is done once, refreshing costs a few matrix products
+ * per fused gate.  It is exact only while the plan's structure holds for the new
+ * matrices, which is checked: a fused gate kept diagonal or as a permutation must still
+ * be one, and every fused gate must stay diagonal on the qubits the planner treated it
+ * as diagonal on (the commutations it used).  A plan made from parameters with special
+ * values (angles of 0 or pi, where rotations become diagonal, permutations or the
+ * identity) can fail that check for general values: make the plan from generic ones.
+ * Host-only, unless the plan's tables are already on a device: then the device is
+ * synchronised and the stale tables freed (the next application uploads the new ones).
+ * Errors: QSV_E_ARG (null or invalid gate, shape differs), QSV_E_UNSUPPORTED (the
+ * structure does not hold, or the plan dropped a fused product as the identity: make
+ * a new plan); on error the plan is unchanged. */
+qsv_status qsv_plan_refresh(qsv_plan p, const qsv_gate* gates, size_t n_gates);
+
 /* Fused gate i (in application order): k, sorted targets, diag flag and the dense
  * 2^k x 2^k FP64 matrix (2*4^k doubles; mat may be NULL).  For host-side checking. */
 qsv_status qsv_plan_fused_gate(qsv_plan p, size_t i, int* k, int targets[5], int* diag,

@@ -66,14 +66,21 @@ struct qsv_state_s {
     size_t work_bytes = 0;
     double* h_work = nullptr;
     size_t hwork_bytes = 0;
-    // plan-table arena for one-shot applications: pinned staging + device block, both
-    // grow-only; tab_ev marks the end of the last copy out of the staging block
-    unsigned char* h_tab = nullptr;
-    size_t htab_bytes = 0;
-    unsigned char* d_tab = nullptr;
-    size_t dtab_bytes = 0;
-    hipEvent_t tab_ev = nullptr;
-    bool tab_ev_pending = false;
+    // plan-table arenas for one-shot applications, used in turn: each a pinned staging
+    // block and a device block, both grow-only, and an event recorded after the last
+    // pass that reads the slot's tables.  With several slots the host can plan and
+    // enqueue up to kTabSlots applications ahead of the device before it has to wait.
+    struct TabSlot {
+        unsigned char* h = nullptr;
+        size_t hbytes = 0;
+        unsigned char* d = nullptr;
+        size_t dbytes = 0;
+        hipEvent_t ev = nullptr;
+        bool pending = false;
+    };
+    static constexpr int kTabSlots = 8;
+    TabSlot tab[kTabSlots];
+    int tab_next = 0;
 };
 
 struct qsv_plan_s {
@@ -483,10 +490,10 @@ qsv_status pauli_sum_apply(qsv_state s, const void* src, void* dst, const std::v
     return QSV_OK;
 }
 
-// Plans and enqueues `gates` on a state (the plan is released after the stream drains).
 // Enqueues every pass of a host plan on the state's stream, its tables copied into the
-// state's arena: one asynchronous copy, no allocation once the arena is large enough,
-// no wait for the device (only for the previous copy out of the staging block).
+// state's next arena slot: one asynchronous copy, no allocation once the slot is large
+// enough, and no wait for the device unless the passes of the application kTabSlots
+// back (which read this slot) are still queued.
 // Uploads the plan's tables into s's arena and enqueues its passes on s's stream; with
 // s2 (same shape and stream) every pass covers both states in one launch; from_zero: the
 // input is |0...0> (the first pass builds it on chip; no passes: s is reset).
@@ -504,58 +511,46 @@ qsv_status enqueue_plan(qsv_state s, const HostPlan& hp, qsv_state s2 = nullptr,
     const size_t o_ipool = o_pool + al(hp.pool.size() * eb);
     const size_t o_apool = o_ipool + al(hp.ipool.size() * sizeof(int));
     const size_t total = std::max<size_t>(o_apool + al(hp.apool.size() * sizeof(float)), 256);
-    if (s->tab_ev_pending) {
-        QSV_HIP(hipEventSynchronize(s->tab_ev));
-        s->tab_ev_pending = false;
+    qsv_state_s::TabSlot& ts = s->tab[s->tab_next];
+    s->tab_next = (s->tab_next + 1) % qsv_state_s::kTabSlots;
+    if (ts.pending) {   // the passes that read this slot's tables (and so its copy) are done
+        QSV_HIP(hipEventSynchronize(ts.ev));
+        ts.pending = false;
     }
-    if (!s->tab_ev) QSV_HIP(hipEventCreateWithFlags(&s->tab_ev, hipEventDisableTiming));
-    if (total > s->htab_bytes) {
-        if (s->h_tab) QSV_HIP(hipHostFree(s->h_tab));
-        s->h_tab = nullptr;
-        s->htab_bytes = 0;
+    if (!ts.ev) QSV_HIP(hipEventCreateWithFlags(&ts.ev, hipEventDisableTiming));
+    if (total > ts.hbytes) {
+        if (ts.h) QSV_HIP(hipHostFree(ts.h));
+        ts.h = nullptr;
+        ts.hbytes = 0;
         const size_t want = std::max<size_t>(total * 2, 1 << 16);
-        QSV_HIP(hipHostMalloc((void**)&s->h_tab, want, hipHostMallocDefault));
-        s->htab_bytes = want;
+        QSV_HIP(hipHostMalloc((void**)&ts.h, want, hipHostMallocDefault));
+        ts.hbytes = want;
     }
-    if (total > s->dtab_bytes) {
-        if (s->d_tab) {
-            QSV_HIP(hipStreamSynchronize(s->stream));   // passes still reading the old block
-            QSV_HIP(hipFree(s->d_tab));
-        }
-        s->d_tab = nullptr;
-        s->dtab_bytes = 0;
+    if (total > ts.dbytes) {
+        if (ts.d) QSV_HIP(hipFree(ts.d));   // no pass reads it any more (event above)
+        ts.d = nullptr;
+        ts.dbytes = 0;
         const size_t want = std::max<size_t>(total * 2, 1 << 16);
-        if (hipMalloc((void**)&s->d_tab, want) != hipSuccess) {
+        if (hipMalloc((void**)&ts.d, want) != hipSuccess) {
             (void)hipGetLastError();
             return fail(QSV_E_OOM, "plan table allocation failed");
         }
-        s->dtab_bytes = want;
+        ts.dbytes = want;
     }
-    unsigned char* h = s->h_tab;
+    unsigned char* h = ts.h;
     if (!hp.ops.empty()) std::memcpy(h + o_ops, hp.ops.data(), hp.ops.size() * sizeof(DevOp));
     pack_pool(hp, h + o_pool);
     if (!hp.ipool.empty()) std::memcpy(h + o_ipool, hp.ipool.data(), hp.ipool.size() * sizeof(int));
     if (!hp.apool.empty()) std::memcpy(h + o_apool, hp.apool.data(), hp.apool.size() * sizeof(float));
-    QSV_HIP(hipMemcpyAsync(s->d_tab, h, total, hipMemcpyHostToDevice, s->stream));
-    QSV_HIP(hipEventRecord(s->tab_ev, s->stream));
-    s->tab_ev_pending = true;
-    unsigned char* d = s->d_tab;
+    QSV_HIP(hipMemcpyAsync(ts.d, h, total, hipMemcpyHostToDevice, s->stream));
+    unsigned char* d = ts.d;
     for (size_t i = 0; i < hp.passes.size(); ++i)
         QSV_HIP(launch_pass(s->dtype, s->buf, hp.pargs[i], hp.pgrid[i], (const DevOp*)(d + o_ops), d + o_pool,
                             (const int*)(d + o_ipool), (const float*)(d + o_apool), s->stream,
                             s2 ? s2->buf : nullptr, from_zero && i == 0, hp.pwide[i] != 0));
+    QSV_HIP(hipEventRecord(ts.ev, s->stream));
+    ts.pending = true;
     return QSV_OK;
-}
-
-// Plans (default options) and enqueues a gate list; asynchronous.
-qsv_status apply_gates(qsv_state s, const std::vector<InGate>& gates)
-{
-    if (gates.empty()) return QSV_OK;
-    PlanOpts o = default_opts(s->dtype);
-    HostPlan hp;
-    std::string err;
-    if (!make_plan(s->n, s->dtype, gates, o, hp, err)) return fail(QSV_E_ARG, err);
-    return enqueue_plan(s, hp);
 }
 
 }  // namespace
@@ -610,9 +605,11 @@ qsv_status qsv_free(qsv_state s)
     if (s->owned) (void)hipFree(s->buf);
     if (s->d_work) (void)hipFree(s->d_work);
     if (s->h_work) (void)hipHostFree(s->h_work);
-    if (s->d_tab) (void)hipFree(s->d_tab);
-    if (s->h_tab) (void)hipHostFree(s->h_tab);
-    if (s->tab_ev) (void)hipEventDestroy(s->tab_ev);
+    for (qsv_state_s::TabSlot& ts : s->tab) {
+        if (ts.d) (void)hipFree(ts.d);
+        if (ts.h) (void)hipHostFree(ts.h);
+        if (ts.ev) (void)hipEventDestroy(ts.ev);
+    }
     delete s;
     return QSV_OK;
 }
@@ -754,6 +751,35 @@ qsv_status qsv_plan_free(qsv_plan p)
         (void)hipFree(p->d_apool);
     }
     delete p;
+    return QSV_OK;
+}
+
+qsv_status qsv_plan_refresh(qsv_plan p, const qsv_gate* gates, size_t n_gates)
+{
+    if (!p) return fail(QSV_E_ARG, "null plan");
+    if (n_gates && !gates) return fail(QSV_E_ARG, "gates is null");
+    std::vector<InGate> in(n_gates);
+    std::string err;
+    for (size_t i = 0; i < n_gates; ++i)
+        if (!read_gate(gates[i], p->hp.n, in[i], err)) return fail(QSV_E_ARG, "gate " + std::to_string(i) + ": " + err);
+    if (!same_shape(p->hp, in)) return fail(QSV_E_ARG, "the gates do not have the shape of the plan's circuit");
+    HostPlan hp = p->hp;
+    if (!refresh_plan(hp, in))
+        return fail(QSV_E_UNSUPPORTED, "the plan's structure does not hold for these gates: make a new plan");
+    if (p->device >= 0) {   // stale device tables: freed once no queued pass can read them
+        DeviceGuard g(p->device);
+        QSV_HIP(hipDeviceSynchronize());
+        (void)hipFree(p->d_ops);
+        (void)hipFree(p->d_pool);
+        (void)hipFree(p->d_ipool);
+        (void)hipFree(p->d_apool);
+        p->d_ops = nullptr;
+        p->d_pool = nullptr;
+        p->d_ipool = nullptr;
+        p->d_apool = nullptr;
+        p->device = -1;
+    }
+    p->hp = std::move(hp);
     return QSV_OK;
 }
 
@@ -1543,99 +1569,156 @@ qsv_status qsv_adjoint_grad(int n, qsv_dtype dtype, const qsv_op* ops, size_t n_
         partial_doubles += d;
     }
 
-    qsv_state phi = nullptr, lam = nullptr;
-    qsv_status st = qsv_alloc(n, dtype, nullptr, 0, stream, &phi);
-    if (st != QSV_OK) return st;
-    st = qsv_alloc(n, dtype, nullptr, 0, stream, &lam);
-    if (st != QSV_OK) {
-        qsv_free(phi);
-        return st;
+    // Parameter vectors run on up to two (phi, lambda) pairs, each pair on a stream of its
+    // own, vector b on pair b % pairs: the host enqueues vector b + 1 while the device
+    // still runs vector b, so the start of one overlaps the end of the other and the
+    // host's planning between vectors leaves no gap.  The second pair is optional (one
+    // pair when it does not fit in memory or B = 1).
+    struct Pair {
+        qsv_state phi = nullptr, lam = nullptr;
+        hipStream_t own = nullptr;   // created here (second pair only)
+        int b = -1;                  // vector in flight on this pair
+    };
+    Pair pair[2];
+    const hipStream_t caller = static_cast<hipStream_t>(stream);
+    qsv_status st = qsv_alloc(n, dtype, nullptr, 0, stream, &pair[0].phi);
+    if (st == QSV_OK) st = qsv_alloc(n, dtype, nullptr, 0, stream, &pair[0].lam);
+    int pairs = st == QSV_OK ? 1 : 0;
+    if (st == QSV_OK && B > 1) {
+        hipEvent_t start = nullptr;
+        bool ok = hipStreamCreateWithFlags(&pair[1].own, hipStreamNonBlocking) == hipSuccess;
+        // work the caller queued before this call comes first on the second stream too
+        ok = ok && hipEventCreateWithFlags(&start, hipEventDisableTiming) == hipSuccess &&
+             hipEventRecord(start, caller) == hipSuccess && hipStreamWaitEvent(pair[1].own, start, 0) == hipSuccess;
+        if (start) (void)hipEventDestroy(start);
+        ok = ok && qsv_alloc(n, dtype, nullptr, 0, pair[1].own, &pair[1].phi) == QSV_OK &&
+             qsv_alloc(n, dtype, nullptr, 0, pair[1].own, &pair[1].lam) == QSV_OK;
+        if (ok) {
+            pairs = 2;
+        } else {   // run on one pair
+            (void)hipGetLastError();
+            qsv_free(pair[1].phi);
+            qsv_free(pair[1].lam);
+            pair[1].phi = pair[1].lam = nullptr;
+            if (pair[1].own) (void)hipStreamDestroy(pair[1].own);
+            pair[1].own = nullptr;
+        }
     }
     // every layer's partials for one parameter vector, read back once per vector
     const size_t pbytes = std::max<size_t>(partial_doubles, 1) * sizeof(double);
-    if ((st = ensure_work(lam, pbytes)) == QSV_OK) st = ensure_hwork(lam, pbytes);
+    for (int p = 0; p < pairs && st == QSV_OK; ++p)
+        if ((st = ensure_work(pair[p].lam, pbytes)) == QSV_OK) st = ensure_hwork(pair[p].lam, pbytes);
     std::vector<double> gv;
+    // Inverse gates undone before each layer's evaluation (the previous layer's
+    // rotations, then the layer's fixed gates), in application order.  Their structure,
+    // and the forward circuit's, is the same for every parameter vector, so each is
+    // planned once from generic angles (no multiples of pi/2, where rotations gain
+    // structure) and refreshed with each vector's matrices (refresh_plan); a vector
+    // whose matrices break a template's structure is planned from scratch.
+    std::vector<std::vector<long long>> undo(layers.size());
+    for (size_t li = 0; li < layers.size(); ++li) {
+        if (li > 0) undo[li] = layers[li - 1].ops;
+        undo[li].insert(undo[li].end(), layers[li].fixed.begin(), layers[li].fixed.end());
+    }
+    auto gates_of = [&](const std::vector<long long>& idx, const double* th, bool inverse) {
+        std::vector<InGate> g;
+        g.reserve(idx.size());
+        for (const long long k : idx) g.push_back(op_gate((size_t)k, th, inverse));
+        return g;
+    };
+    std::vector<long long> all_ops(n_ops);
+    for (size_t i = 0; i < n_ops; ++i) all_ops[i] = (long long)i;
+    std::vector<double> th_generic((size_t)std::max(P, 1));
+    for (size_t j = 0; j < th_generic.size(); ++j) th_generic[j] = 0.5 + 0.7548776662466927 * (double)(j + 1);
+    HostPlan fwd_tmpl;
+    std::vector<HostPlan> undo_tmpl(layers.size());
+    if (st == QSV_OK && n_ops &&
+        !make_plan(n, dtype, gates_of(all_ops, th_generic.data(), false), default_opts(dtype), fwd_tmpl, err))
+        st = fail(QSV_E_ARG, err);
+    for (size_t li = 0; li < layers.size() && st == QSV_OK; ++li)
+        if (!undo[li].empty() &&
+            !make_plan(n, dtype, gates_of(undo[li], th_generic.data(), true), default_opts(dtype), undo_tmpl[li], err))
+            st = fail(QSV_E_ARG, err);
+    // a template refreshed with a vector's gates, or a plan made for them
+    auto plan_for = [&](const HostPlan& tmpl, const std::vector<InGate>& g, HostPlan& hp) -> qsv_status {
+        hp = tmpl;
+        if (refresh_plan(hp, g)) return QSV_OK;
+        if (!make_plan(n, dtype, g, default_opts(dtype), hp, err)) return fail(QSV_E_ARG, err);
+        return QSV_OK;
+    };
     // the forward circuit's plan for vector b; the next vector's is built on the host
     // while the device runs the current one
     auto plan_forward = [&](int b, HostPlan& hp) -> qsv_status {
+        if (!n_ops) return QSV_OK;
+        return plan_for(fwd_tmpl, gates_of(all_ops, params + (size_t)b * P, false), hp);
+    };
+    // enqueue vector b on pair pr: forward, energy, co-state, reverse sweep, partials copy
+    auto enqueue_vector = [&](int b, Pair& pr, const HostPlan& fwd) -> qsv_status {
+        qsv_state phi = pr.phi, lam = pr.lam;
         const double* th = params + (size_t)b * P;
-        std::vector<InGate> fwd;
-        fwd.reserve(n_ops);
-        for (size_t i = 0; i < n_ops; ++i) fwd.push_back(op_gate(i, th, false));
-        if (fwd.empty()) return QSV_OK;
-        if (!make_plan(n, dtype, fwd, default_opts(dtype), hp, err)) return fail(QSV_E_ARG, err);
+        qsv_status s2 = QSV_OK;
+        // forward: phi = U(theta)|0>
+        if (n_ops) {
+            if ((s2 = enqueue_plan(phi, fwd, nullptr, true)) != QSV_OK) return s2;
+        } else if ((s2 = qsv_reset(phi)) != QSV_OK) {
+            return s2;
+        }
+        // energy (partials read back with the gradients) and co-state lambda = H phi
+        hipError_t he = launch_elements(dtype, phi->buf, phi->buf, Ge, lam->d_work, lam->stream);
+        if (he != hipSuccess) return fail(QSV_E_DEVICE, std::string("adjoint: ") + hipGetErrorString(he));
+        if ((s2 = pauli_sum_apply(lam, phi->buf, lam->buf, hterms)) != QSV_OK) return s2;
+        // reverse sweep, asynchronous: uncompute (fixed gates and the previous layer,
+        // one plan applied to both states), then the layer's Im <lambda|P_j|phi>
+        for (size_t li = 0; li < layers.size(); ++li) {
+            if (!undo[li].empty()) {
+                HostPlan hp;
+                if ((s2 = plan_for(undo_tmpl[li], gates_of(undo[li], th, true), hp)) != QSV_OK) return s2;
+                if ((s2 = enqueue_plan(phi, hp, lam)) != QSV_OK) return s2;   // one launch per pass, both states
+            }
+            he = launch_elements(dtype, lam->buf, phi->buf, layers[li].G, lam->d_work, lam->stream);
+            if (he != hipSuccess) return fail(QSV_E_DEVICE, std::string("adjoint: ") + hipGetErrorString(he));
+        }
+        if (hipMemcpyAsync(lam->h_work, lam->d_work, pbytes, hipMemcpyDeviceToHost, lam->stream) != hipSuccess)
+            return fail(QSV_E_DEVICE, "adjoint: partials read-back failed");
+        pr.b = b;
+        return QSV_OK;
+    };
+    // wait for the vector in flight on pair pr and combine its partials
+    auto finish_vector = [&](Pair& pr) -> qsv_status {
+        if (pr.b < 0) return QSV_OK;
+        const int b = pr.b;
+        pr.b = -1;
+        if (hipStreamSynchronize(pr.lam->stream) != hipSuccess) return fail(QSV_E_DEVICE, "adjoint: partials read-back failed");
+        double* gb = grad + (size_t)b * P;
+        for (int j = 0; j < P; ++j) gb[j] = 0.0;
+        for (const Layer& Ly : layers) {
+            combine_elements(Ly.G, pr.lam->h_work, Ly.ops.size(), gv);
+            for (size_t l = 0; l < Ly.ops.size(); ++l) gb[ops[Ly.ops[l]].param] += gv[l];
+        }
+        combine_elements(Ge, pr.lam->h_work, hterms.size(), gv);
+        NS e;
+        for (size_t t = 0; t < hterms.size(); ++t) e.add(hterms[t].coeff * gv[t]);
+        energy[b] = e.value();
         return QSV_OK;
     };
     HostPlan fwd_cur, fwd_next;
     if (st == QSV_OK) st = plan_forward(0, fwd_cur);
     for (int b = 0; b < B && st == QSV_OK; ++b) {
-        const double* th = params + (size_t)b * P;
-        double* gb = grad + (size_t)b * P;
-        for (int j = 0; j < P; ++j) gb[j] = 0.0;
-        // forward: phi = U(theta)|0>
-        if (n_ops) {
-            if ((st = enqueue_plan(phi, fwd_cur, nullptr, true)) != QSV_OK) break;
-        } else if ((st = qsv_reset(phi)) != QSV_OK) {
-            break;
-        }
-        // energy (partials read back with the gradients) and co-state lambda = H phi
-        {
-            const hipError_t he = launch_elements(dtype, phi->buf, phi->buf, Ge, lam->d_work, lam->stream);
-            if (he != hipSuccess) {
-                st = fail(QSV_E_DEVICE, std::string("adjoint: ") + hipGetErrorString(he));
-                break;
-            }
-        }
-        if ((st = pauli_sum_apply(lam, phi->buf, lam->buf, hterms)) != QSV_OK) break;
-        // reverse sweep, asynchronous: uncompute (fixed gates and the previous layer,
-        // one plan applied to both states), then the layer's Im <lambda|P_j|phi>
-        std::vector<InGate> pending;   // inverse gates still to apply, in application order
-        for (size_t li = 0; li < layers.size() && st == QSV_OK; ++li) {
-            const Layer& Ly = layers[li];
-            for (const long long k : Ly.fixed) pending.push_back(op_gate((size_t)k, th, true));
-            if (!pending.empty()) {
-                HostPlan hp;
-                if (!make_plan(n, dtype, pending, default_opts(dtype), hp, err)) {
-                    st = fail(QSV_E_ARG, err);
-                    break;
-                }
-                if (phi->stream == lam->stream) {   // one launch per pass for both vectors
-                    if ((st = enqueue_plan(phi, hp, lam)) != QSV_OK) break;
-                } else {
-                    if ((st = enqueue_plan(phi, hp)) != QSV_OK) break;
-                    if ((st = enqueue_plan(lam, hp)) != QSV_OK) break;
-                }
-                pending.clear();
-            }
-            const hipError_t he = launch_elements(dtype, lam->buf, phi->buf, Ly.G, lam->d_work, lam->stream);
-            if (he != hipSuccess) {
-                st = fail(QSV_E_DEVICE, std::string("adjoint: ") + hipGetErrorString(he));
-                break;
-            }
-            for (const long long k : Ly.ops) pending.push_back(op_gate((size_t)k, th, true));
-        }
-        if (st != QSV_OK) break;
-        if (hipMemcpyAsync(lam->h_work, lam->d_work, pbytes, hipMemcpyDeviceToHost, lam->stream) != hipSuccess) {
-            st = fail(QSV_E_DEVICE, "adjoint: partials read-back failed");
-            break;
-        }
+        Pair& pr = pair[b % pairs];
+        if ((st = finish_vector(pr)) != QSV_OK) break;   // vector b - pairs
+        if ((st = enqueue_vector(b, pr, fwd_cur)) != QSV_OK) break;
         if (b + 1 < B && (st = plan_forward(b + 1, fwd_next)) != QSV_OK) break;
-        if (hipStreamSynchronize(lam->stream) != hipSuccess) {
-            st = fail(QSV_E_DEVICE, "adjoint: partials read-back failed");
-            break;
-        }
-        for (const Layer& Ly : layers) {
-            combine_elements(Ly.G, lam->h_work, Ly.ops.size(), gv);
-            for (size_t l = 0; l < Ly.ops.size(); ++l) gb[ops[Ly.ops[l]].param] += gv[l];
-        }
-        combine_elements(Ge, lam->h_work, hterms.size(), gv);
-        NS e;
-        for (size_t t = 0; t < hterms.size(); ++t) e.add(hterms[t].coeff * gv[t]);
-        energy[b] = e.value();
         std::swap(fwd_cur, fwd_next);
     }
-    qsv_free(phi);
-    qsv_free(lam);
+    for (int p = 0; p < pairs; ++p) {
+        const qsv_status s2 = finish_vector(pair[p]);
+        if (st == QSV_OK) st = s2;
+    }
+    for (int p = 0; p < 2; ++p) {
+        qsv_free(pair[p].phi);   // waits for the pair's stream
+        qsv_free(pair[p].lam);
+        if (pair[p].own) (void)hipStreamDestroy(pair[p].own);
+    }
     return st;
 }
 

@@ -260,6 +260,7 @@ FGate canonical(const InGate& g, int index)
     f.kind = classify(f.m, f.k);
     f.dq = diag_qubit_mask(f);
     f.first = index;
+    f.mem.assign(1, index);
     return f;
 }
 
@@ -341,6 +342,8 @@ FGate fuse_pair(const FGate& u, const FGate& v, int kmax, bool& ok)
     f.dq = diag_qubit_mask(f);
     f.first = std::min(u.first, v.first);
     f.members = u.members + v.members;
+    f.mem = u.mem;
+    f.mem.insert(f.mem.end(), v.mem.begin(), v.mem.end());
     return f;
 }
 
@@ -776,77 +779,21 @@ bool schedule_passes(int n, const std::vector<FGate>& fused, const PlanOpts& o, 
     return true;
 }
 
-}  // namespace
-
-bool make_plan(int n, int dtype, const std::vector<InGate>& gates, const PlanOpts& o,
-               HostPlan& P, std::string& err)
+// Device tables of a planned circuit (op descriptors, matrix pools, staged operand
+// blocks, pass arguments) and the arithmetic statistics, from P.fused and P.passes.
+void build_device_tables(HostPlan& P)
 {
-    P = HostPlan();
-    P.n = n;
-    P.dtype = dtype;
-    P.o = o;
-    P.gates_in = gates.size();
-    if (o.kmax < 1 || o.kmax > kMaxK) { err = "kmax must be in [1, 5]"; return false; }
-    if (o.low_qubits < 1 || o.low_qubits > kLogThreads) { err = "low_qubits must be in [1, 8]"; return false; }
-    if (o.tile_qubits < o.low_qubits + 1 || o.tile_qubits < kMaxK + 1 || o.tile_qubits > kMaxTileQubits) {
-        err = "tile_qubits must be in [max(low_qubits+1, 6), 13]";
-        return false;
-    }
-
-    // ---- DAG (Section 5.1): immediate predecessor per qubit
-    std::vector<Node> nodes(gates.size());
-    std::vector<int> last(n, -1);
-    for (size_t i = 0; i < gates.size(); ++i) {
-        Node& nd = nodes[i];
-        nd.g = canonical(gates[i], (int)i);
-        for (int j = 0; j < nd.g.k; ++j) {
-            const int x = nd.g.q[j];
-            nd.prev[j] = last[x];
-            nd.next[j] = -1;
-            if (last[x] >= 0) {
-                Node& p = nodes[last[x]];
-                p.next[slot_of(p, x)] = (int)i;
-            }
-            last[x] = (int)i;
-        }
-    }
-
-    // ---- Algorithm 2 on the per-qubit DAG; with `commute`, diagonal ops are then also
-    // merged across the commutation-aware DAG, and the whole fusion is run a second time
-    // on that DAG: the plan with fewer passes (then less arithmetic) is kept
-    {
-        if (o.fuse == 1) run_fusion(nodes, o);
-        std::vector<FGate> in;
-        for (const int v : topo_order(nodes)) in.push_back(nodes[v].g);
-        if (o.fuse == 1 && o.commute) in = fuse_commuting(in, n, o, true);
-        for (FGate& g : in)
-            if (!is_identity(g)) P.fused.push_back(std::move(g));
-        if (o.fuse == 1 && o.commute) merge_diagonals(P.fused, o.kmax);
-    }
-    if (!schedule_passes(n, P.fused, o, P.passes, err)) return false;
-    if (o.fuse == 1 && o.commute) {
-        std::vector<FGate> in;
-        in.reserve(gates.size());
-        for (size_t i = 0; i < gates.size(); ++i) in.push_back(canonical(gates[i], (int)i));
-        std::vector<FGate> alt;
-        for (FGate& g : fuse_commuting(in, n, o, false))
-            if (!is_identity(g)) alt.push_back(std::move(g));
-        merge_diagonals(alt, o.kmax);
-        std::vector<PassPlan> alt_passes;
-        if (!schedule_passes(n, alt, o, alt_passes, err)) return false;
-        auto arith = [&](const std::vector<FGate>& f) {
-            double a = 0;
-            for (const FGate& g : f) a += op_cost(g, o);
-            return a;
-        };
-        if (alt_passes.size() < P.passes.size() ||
-            (alt_passes.size() == P.passes.size() && arith(alt) < arith(P.fused))) {
-            P.fused.swap(alt);
-            P.passes.swap(alt_passes);
-        }
-    }
-
-    // ---- device tables
+    const int n = P.n, dtype = P.dtype;
+    const PlanOpts& o = P.o;
+    P.ops.clear();
+    P.pargs.clear();
+    P.pgrid.clear();
+    P.pwide.clear();
+    P.pool.clear();
+    P.ipool.clear();
+    P.apool.clear();
+    P.dense_ops = P.diag_ops = P.perm_ops = P.mfma_ops = 0;
+    P.fma_per_amp = P.mfma_fma_per_amp = 0;
     for (const PassPlan& pp : P.passes) {
         PassArgs a{};
         a.m = (int)pp.active.size();
@@ -963,6 +910,176 @@ bool make_plan(int n, int dtype, const std::vector<InGate>& gates, const PlanOpt
         P.pargs.push_back(a);
         P.pgrid.push_back(1ll << (n - a.m));
     }
+}
+
+}  // namespace
+
+bool make_plan(int n, int dtype, const std::vector<InGate>& gates, const PlanOpts& o,
+               HostPlan& P, std::string& err)
+{
+    P = HostPlan();
+    P.n = n;
+    P.dtype = dtype;
+    P.o = o;
+    P.gates_in = gates.size();
+    for (const InGate& g : gates) {
+        P.shape.push_back(g.k);
+        P.shape.insert(P.shape.end(), g.t, g.t + g.k);
+    }
+    if (o.kmax < 1 || o.kmax > kMaxK) { err = "kmax must be in [1, 5]"; return false; }
+    if (o.low_qubits < 1 || o.low_qubits > kLogThreads) { err = "low_qubits must be in [1, 8]"; return false; }
+    if (o.tile_qubits < o.low_qubits + 1 || o.tile_qubits < kMaxK + 1 || o.tile_qubits > kMaxTileQubits) {
+        err = "tile_qubits must be in [max(low_qubits+1, 6), 13]";
+        return false;
+    }
+
+    // ---- DAG (Section 5.1): immediate predecessor per qubit
+    std::vector<Node> nodes(gates.size());
+    std::vector<int> last(n, -1);
+    for (size_t i = 0; i < gates.size(); ++i) {
+        Node& nd = nodes[i];
+        nd.g = canonical(gates[i], (int)i);
+        for (int j = 0; j < nd.g.k; ++j) {
+            const int x = nd.g.q[j];
+            nd.prev[j] = last[x];
+            nd.next[j] = -1;
+            if (last[x] >= 0) {
+                Node& p = nodes[last[x]];
+                p.next[slot_of(p, x)] = (int)i;
+            }
+            last[x] = (int)i;
+        }
+    }
+
+    // ---- Algorithm 2 on the per-qubit DAG; with `commute`, diagonal ops are then also
+    // merged across the commutation-aware DAG, and the whole fusion is run a second time
+    // on that DAG: the plan with fewer passes (then less arithmetic) is kept
+    {
+        if (o.fuse == 1) run_fusion(nodes, o);
+        std::vector<FGate> in;
+        for (const int v : topo_order(nodes)) in.push_back(nodes[v].g);
+        if (o.fuse == 1 && o.commute) in = fuse_commuting(in, n, o, true);
+        for (FGate& g : in)
+            if (!is_identity(g)) P.fused.push_back(std::move(g));
+        if (o.fuse == 1 && o.commute) merge_diagonals(P.fused, o.kmax);
+    }
+    if (!schedule_passes(n, P.fused, o, P.passes, err)) return false;
+    if (o.fuse == 1 && o.commute) {
+        std::vector<FGate> in;
+        in.reserve(gates.size());
+        for (size_t i = 0; i < gates.size(); ++i) in.push_back(canonical(gates[i], (int)i));
+        std::vector<FGate> alt;
+        for (FGate& g : fuse_commuting(in, n, o, false))
+            if (!is_identity(g)) alt.push_back(std::move(g));
+        merge_diagonals(alt, o.kmax);
+        std::vector<PassPlan> alt_passes;
+        if (!schedule_passes(n, alt, o, alt_passes, err)) return false;
+        auto arith = [&](const std::vector<FGate>& f) {
+            double a = 0;
+            for (const FGate& g : f) a += op_cost(g, o);
+            return a;
+        };
+        if (alt_passes.size() < P.passes.size() ||
+            (alt_passes.size() == P.passes.size() && arith(alt) < arith(P.fused))) {
+            P.fused.swap(alt);
+            P.passes.swap(alt_passes);
+        }
+    }
+
+    build_device_tables(P);
+    return true;
+}
+
+
+namespace {
+
+// M <- E(g) M for a d x d matrix M over the fused op's targets: g's local bit j sits at
+// M's local bit pos[j].  Each column of M is transformed like a state vector.
+void apply_on_rows(std::vector<cd>& M, int d, const InGate& g, const int* pos)
+{
+    const int dg = 1 << g.k;
+    int mask = 0;
+    for (int j = 0; j < g.k; ++j) mask |= 1 << pos[j];
+    int rows[1 << kMaxK];
+    cd in[1 << kMaxK];
+    for (int r0 = 0; r0 < d; ++r0) {
+        if (r0 & mask) continue;
+        for (int a = 0; a < dg; ++a) {
+            int r = r0;
+            for (int j = 0; j < g.k; ++j)
+                if ((a >> j) & 1) r |= 1 << pos[j];
+            rows[a] = r;
+        }
+        for (int c = 0; c < d; ++c) {
+            for (int a = 0; a < dg; ++a) in[a] = M[(size_t)rows[a] * d + c];
+            for (int a = 0; a < dg; ++a) {
+                double re = 0, im = 0;   // plain products: every value here is finite
+                for (int b = 0; b < dg; ++b) {
+                    const cd u = g.m[(size_t)a * dg + b];
+                    re += u.real() * in[b].real() - u.imag() * in[b].imag();
+                    im += u.real() * in[b].imag() + u.imag() * in[b].real();
+                }
+                M[(size_t)rows[a] * d + c] = cd(re, im);
+            }
+        }
+    }
+}
+
+}  // namespace
+
+bool same_shape(const HostPlan& P, const std::vector<InGate>& gates)
+{
+    if (gates.size() != P.gates_in) return false;
+    size_t at = 0;
+    for (const InGate& g : gates) {
+        if (at + 1 + (size_t)g.k > P.shape.size() || P.shape[at] != g.k) return false;
+        for (int j = 0; j < g.k; ++j)
+            if (P.shape[at + 1 + (size_t)j] != g.t[j]) return false;
+        at += 1 + (size_t)g.k;
+    }
+    return at == P.shape.size();
+}
+
+bool refresh_plan(HostPlan& P, const std::vector<InGate>& gates)
+{
+    if (!same_shape(P, gates)) return false;
+    size_t covered = 0;
+    for (const FGate& f : P.fused) covered += f.mem.size();
+    if (covered != gates.size()) return false;   // a product was dropped as the identity
+    std::vector<std::vector<cd>> mats(P.fused.size());
+    for (size_t fi = 0; fi < P.fused.size(); ++fi) {
+        const FGate& f = P.fused[fi];
+        const int d = 1 << f.k;
+        std::vector<cd>& M = mats[fi];
+        M.assign((size_t)d * d, cd(0, 0));
+        for (int r = 0; r < d; ++r) M[(size_t)r * d + r] = cd(1, 0);
+        for (const int i : f.mem) {
+            if (i < 0 || (size_t)i >= gates.size()) return false;
+            const InGate& g = gates[(size_t)i];
+            int pos[kMaxK];
+            for (int j = 0; j < g.k; ++j) {
+                pos[j] = -1;
+                for (int t = 0; t < f.k; ++t)
+                    if (f.q[t] == g.t[j]) pos[j] = t;
+                if (pos[j] < 0) return false;   // not the circuit the plan was made for
+            }
+            if ((int)g.m.size() != (1 << (2 * g.k))) return false;
+            apply_on_rows(M, d, g, pos);
+        }
+        // the structure the planner used must still hold
+        FGate probe;
+        probe.k = f.k;
+        for (int j = 0; j < f.k; ++j) probe.q[j] = f.q[j];
+        probe.m = M;
+        if ((diag_qubit_mask(probe) & f.dq) != f.dq) return false;
+        if (f.kind == OP_DIAG || f.kind == OP_PERM) {
+            for (int r = 0; r < d; ++r)
+                for (int c = 0; c < d; ++c)
+                    if (f.m[(size_t)r * d + c] == cd(0, 0) && M[(size_t)r * d + c] != cd(0, 0)) return false;
+        }
+    }
+    for (size_t fi = 0; fi < P.fused.size(); ++fi) P.fused[fi].m.swap(mats[fi]);
+    build_device_tables(P);
     return true;
 }
 

@@ -30,6 +30,8 @@ struct FGate {
     int members = 1;
     unsigned long long dq = 0;  // physical qubits on which the op is diagonal (it commutes
                                 // with Z on each of them): exactly-zero couplings
+    std::vector<int> mem;       // circuit indices of the members, in the order the fused
+                                // matrix applies them
 };
 
 struct PlanOpts {
@@ -61,6 +63,7 @@ struct HostPlan {
     int dtype = 0;
     PlanOpts o;
     size_t gates_in = 0;
+    std::vector<int> shape;        // the input circuit's shape: per gate k, then its k targets
     std::vector<FGate> fused;
     std::vector<PassPlan> passes;
     // device-format tables
@@ -108,5 +111,22 @@ int classify(const std::vector<cd>& m, int k);
 // Runs fusion (when o.fuse) and pass scheduling; fills every field of `out`.
 bool make_plan(int n, int dtype, const std::vector<InGate>& gates, const PlanOpts& o,
                HostPlan& out, std::string& err);
+
+// Re-fills plan P, made by make_plan for a circuit of the same shape (same gate count,
+// same targets gate by gate), with the matrices of `gates`: every fused matrix is
+// rebuilt as the product of its members' new matrices in the plan's order, and the
+// device tables are rebuilt; the fusion and the passes are kept.  This is exact when
+// the plan's structure still holds for the new matrices, which is checked: a diagonal
+// op must stay diagonal, a permutation keep its pattern, and every op stay diagonal on
+// the qubits the planner took it to be diagonal on (the commutations it relied on).
+// Returns false, leaving P unchanged, when a check fails or a fused product was dropped
+// as the identity; the caller then plans from scratch.  Meant for circuits whose
+// structure is fixed while their parameters change (gradient sweeps over parameter
+// vectors), with a template plan made from parameters with no special values.
+bool refresh_plan(HostPlan& P, const std::vector<InGate>& gates);
+
+// True when `gates` has the shape of the circuit P was made for: the same gate count and,
+// gate by gate, the same targets in the same order.
+bool same_shape(const HostPlan& P, const std::vector<InGate>& gates);
 
 }  // namespace qsv

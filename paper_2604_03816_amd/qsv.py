@@ -71,7 +71,7 @@ class COp(ctypes.Structure):
 EXPORTS = [
     "qsv_last_error", "qsv_version", "qsv_alloc", "qsv_free", "qsv_reset", "qsv_info", "qsv_get_state",
     "qsv_set_state", "qsv_gate_matrix", "qsv_plan_create", "qsv_plan_free", "qsv_plan_get_stats",
-    "qsv_plan_fused_gate", "qsv_plan_pass_info", "qsv_plan_pass_ops", "qsv_plan_emulate", "qsv_plan_apply",
+    "qsv_plan_refresh", "qsv_plan_fused_gate", "qsv_plan_pass_info", "qsv_plan_pass_ops", "qsv_plan_emulate", "qsv_plan_apply",
     "qsv_plan_apply_range", "qsv_plan_apply_zero",
     "qsv_apply_fused", "qsv_sync", "qsv_norm", "qsv_norm_noalloc", "qsv_expval_pauli", "qsv_probs", "qsv_sample", "qsv_adjoint_grad",
     "qsv_dm_apply", "qsv_dm_probs", "qsv_dm_expval_pauli", "qsv_precision_select",
@@ -103,6 +103,7 @@ def lib():
     L.qsv_plan_create.argtypes = [i, i, ctypes.POINTER(Gate), sz, ctypes.POINTER(PlanOpts), ctypes.POINTER(vp)]
     L.qsv_plan_free.argtypes = [vp]
     L.qsv_plan_get_stats.argtypes = [vp, ctypes.POINTER(PlanStats)]
+    L.qsv_plan_refresh.argtypes = [vp, ctypes.POINTER(Gate), sz]
     L.qsv_plan_fused_gate.argtypes = [vp, sz, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i), dp]
     L.qsv_plan_pass_info.argtypes = [vp, sz, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]
     L.qsv_plan_pass_ops.argtypes = [vp, sz, ctypes.POINTER(i)]
@@ -269,6 +270,12 @@ class Plan:
         st = PlanStats()
         check(lib().qsv_plan_get_stats(self.h, ctypes.byref(st)))
         return st.as_dict()
+
+    def refresh(self, ops: Iterable) -> None:
+        """qsv_plan_refresh: the same circuit shape with new matrices (raises QSVError
+        when the plan's structure does not hold for them)."""
+        gl = ops if isinstance(ops, (GateList, ArrayGateList)) else GateList(ops)
+        check(lib().qsv_plan_refresh(self.h, gl.arr, gl.n))
 
     def fused_gates(self) -> List[Tuple[Tuple[int, ...], np.ndarray, bool]]:
         out = []

@@ -38,6 +38,25 @@ def test_hea_tfim_12q_matches_parameter_shift(qsv, dtype):
         assert rel(G[b], g_ref) <= REL[dtype], rel(G[b], g_ref)
 
 
+def test_special_angles_and_many_vectors(qsv):
+    """Vectors with angles of 0 and multiples of pi/2 (rotations become the identity,
+    diagonal or permutations) among generic ones, more vectors than the sweep keeps in
+    flight: every gradient against the oracle's parameter shift."""
+    n, layers = 8, 3
+    tpl = C.hea(n, layers, ring=True)
+    terms = C.tfim_terms(n)
+    params = C.hea_params(n, layers, seed=21, batch=5)
+    params[1][:] = 0.0
+    params[2][::2] = np.pi / 2
+    params[3][1::3] = np.pi
+    E, G = qsv.adjoint_grad(n, tpl, params, terms, "c128")
+    for b in range(5):
+        e_ref = oracle.energy(n, tpl, params[b], terms)
+        g_ref = oracle.param_shift_grad(n, tpl, params[b], terms)
+        assert abs(E[b] - e_ref) <= 1e-12 * max(1.0, abs(e_ref)), b
+        assert np.max(np.abs(G[b] - g_ref)) <= 1e-10, b
+
+
 def test_24q_complex64_against_complex128_and_finite_differences(qsv):
     """At the gradient workload's size (24 qubits, 8 layers, 384 parameters, TFIM):
     complex64 gradients within 1e-3 relative error of complex128 ones, and complex128

@@ -191,6 +191,23 @@ def test_plan_reuse_and_pass_ranges(qsv):
         s.apply_plan(plan, npass, 1)
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_refreshed_plan_on_device(qsv, dtype):
+    """qsv_plan_refresh on a plan already applied on the device: the stale tables are
+    replaced, and the refreshed plan applies the ansatz with the new angles (oracle)."""
+    n, L = 20, 3
+    tmpl = C.hea(n, L, ring=True)
+    plan = qsv.Plan(n, dtype, C.bind(tmpl, C.hea_params(n, L, seed=31)))
+    s = qsv.State(n, dtype)
+    for seed in (32, 33):
+        ops = C.bind(tmpl, C.hea_params(n, L, seed=seed))
+        plan.refresh(ops)
+        s.apply_plan_zero(plan)
+        check_state(s.get(), oracle.simulate(n, ops), dtype, "seed %d" % seed)
+    s.free()
+    plan.free()
+
+
 # ------------------------------------------------------------------ reductions
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])

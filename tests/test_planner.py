@@ -396,3 +396,116 @@ def test_window_tiles_cut_passes_on_brickwork():
     assert qsv.Plan(n, "c128", ops).stats()["passes"] <= 26
     for _, active in qsv.Plan(n, "c64", ops).passes():
         assert len(active) == 12 and set(range(4)) <= set(active)
+
+
+# ------------------------------------------------------------------ plan refresh
+
+def _rotation_mix(n, count, rng, angles=None):
+    """Rotations (RX, RY, RZ) with fixed gates (H, T, CNOT, CZ, a Haar 2-qubit unitary)
+    between them; `angles` overrides the rotation angles in order."""
+    ops, a = [], 0
+    fixed = rand_unitary(4, np.random.default_rng(99))
+    for _ in range(count):
+        kind = rng.integers(0, 8)
+        q = int(rng.integers(0, n))
+        r = int((q + 1 + rng.integers(0, n - 1)) % n)
+        if kind < 3:
+            th = float(rng.uniform(-np.pi, np.pi))
+            if angles is not None:
+                th = float(angles[a])
+            a += 1
+            ops.append(C.Op(("RX", "RY", "RZ")[kind], (q,), (th,)))
+        elif kind == 3:
+            ops.append(C.Op("H", (q,)))
+        elif kind == 4:
+            ops.append(C.Op("T", (q,)))
+        elif kind == 5:
+            ops.append(C.Op("CNOT", (q, r)))
+        elif kind == 6:
+            ops.append(C.Op("CZ", (q, r)))
+        else:
+            ops.append(C.Op("U", (q, r), matrix=fixed))
+    return ops, a
+
+
+def _refreshed_equals_oracle(n, plan, ops, seed):
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+    psi0 = np.ascontiguousarray(v / np.linalg.norm(v))
+    ref = oracle.simulate(n, ops, psi=psi0.copy())
+    return np.max(np.abs(plan.emulate(psi0) - ref))
+
+
+@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_plan_refresh_reproduces_the_circuit_with_new_angles(seed, dtype):
+    """A plan made from generic angles, refreshed with other angles, applies the circuit
+    with those angles (FP64 oracle) and keeps its passes; the ansatz and a mix of
+    rotations with fixed gates, under the default and several tile geometries."""
+    n, L = 10, 4
+    tmpl = C.hea(n, L, ring=True)
+    for opts in ({}, {"tile_qubits": 7, "low_qubits": 3}, {"kmax": 3}, {"commute": -1}):
+        plan = qsv.Plan(n, dtype, C.bind(tmpl, C.hea_params(n, L, seed=100 + seed)), **opts)
+        passes = plan.stats()["passes"]
+        for s2 in range(2):
+            ops = C.bind(tmpl, C.hea_params(n, L, seed=200 + 10 * seed + s2))
+            plan.refresh(ops)
+            assert plan.stats()["passes"] == passes
+            assert _refreshed_equals_oracle(n, plan, ops, seed) < 1e-12, opts
+    rng = np.random.default_rng(300 + seed)
+    ops, na = _rotation_mix(9, 120, rng)
+    plan = qsv.Plan(9, dtype, ops, tile_qubits=7, low_qubits=2)
+    for s2 in range(2):
+        new_ops, _ = _rotation_mix(9, 120, np.random.default_rng(300 + seed),
+                                   angles=np.random.default_rng(400 + s2).uniform(-np.pi, np.pi, na))
+        plan.refresh(new_ops)
+        assert _refreshed_equals_oracle(9, plan, new_ops, seed) < 1e-12
+
+
+@pytest.mark.parametrize("special", [0.0, np.pi / 2, np.pi, -np.pi])
+def test_plan_refresh_with_special_angles_is_exact_or_refused(special):
+    """Angles of 0 or multiples of pi/2 give rotations extra structure (identity,
+    diagonal, permutation).  Refreshing a generic plan with them must still be exact;
+    a plan made from them may be refused for generic angles, but never be wrong."""
+    n = 9
+    rng = np.random.default_rng(5)
+    ops, na = _rotation_mix(n, 100, rng)
+    generic = np.random.default_rng(6).uniform(-np.pi, np.pi, na)
+    sp = np.where(np.arange(na) % 3 == 0, special, generic)
+    sp_ops, _ = _rotation_mix(n, 100, np.random.default_rng(5), angles=sp)
+    gen_ops, _ = _rotation_mix(n, 100, np.random.default_rng(5), angles=generic)
+    for dtype in ("c64", "c128"):
+        plan = qsv.Plan(n, dtype, gen_ops)
+        plan.refresh(sp_ops)
+        assert _refreshed_equals_oracle(n, plan, sp_ops, 1) < 1e-12
+        plan = qsv.Plan(n, dtype, sp_ops)
+        try:
+            plan.refresh(gen_ops)
+        except qsv.QSVError as e:
+            assert e.status == 4   # QSV_E_UNSUPPORTED: plan again
+        else:
+            assert _refreshed_equals_oracle(n, plan, gen_ops, 1) < 1e-12
+
+
+def test_plan_refresh_refuses_what_it_cannot_refresh():
+    n = 6
+    base = [C.Op("H", (0,)), C.Op("RZ", (1,), (0.3,)), C.Op("RZ", (2,), (0.4,)), C.Op("CNOT", (0, 3))]
+    plan = qsv.Plan(n, "c128", base)
+    assert plan.stats()["diag_ops"] == 1            # RZ(1) and RZ(2) merged
+    # a diagonal op would become dense: refused, and the plan is left as it was
+    with pytest.raises(qsv.QSVError) as e:
+        plan.refresh([base[0], C.Op("RX", (1,), (0.3,)), base[2], base[3]])
+    assert e.value.status == 4
+    assert _refreshed_equals_oracle(n, plan, base, 2) < 1e-12
+    # another shape (targets or gate count): an argument error
+    with pytest.raises(qsv.QSVError) as e:
+        plan.refresh([base[0], C.Op("RZ", (4,), (0.3,)), base[2], base[3]])
+    assert e.value.status == 1
+    with pytest.raises(qsv.QSVError) as e:
+        plan.refresh(base[:3])
+    assert e.value.status == 1
+    # a plan that dropped an identity product cannot be refreshed
+    ident = qsv.Plan(n, "c64", [C.Op("X", (3,)), C.Op("X", (3,)), C.Op("H", (1,))])
+    with pytest.raises(qsv.QSVError) as e:
+        ident.refresh([C.Op("X", (3,)), C.Op("Y", (3,)), C.Op("H", (1,))])
+    assert e.value.status == 4
