@@ -277,9 +277,12 @@ __device__ void op_dense(C* __restrict__ lds, int T, const DevOp& op, cptr<C> __
 // K = 4 steps), and receives output rows 8 rb + 2 q and 8 rb + 2 q + 1 of row block rb
 // (A[i][k] sits in lane i + 16 k and B[k][j] in lane j + 16 k in both precisions; the
 // output rows' order differs between the FP32 and FP64 instructions, which the planner's
-// arrangement of the A operand rows absorbs).  The A operands (staged in LDS once per
-// pass) stay in registers for the whole op.  All reads of a block precede its writes, so the update is in place; waves
-// own disjoint groups.
+// lanes' choice of A rows absorbs).  The op's complex matrix is staged in LDS once per
+// pass, D x D row-major in the state's precision (half the bytes of its real embedding
+// [[Re, -Im], [Im, Re]]); each lane reads the complex entries of its A-operand slots
+// once per op and keeps the real-embedded values in registers for the whole op.  All
+// reads of a block precede its writes, so the update is in place; waves own disjoint
+// groups.
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 template <typename C, int K, int NT = kThreads>
@@ -287,17 +290,35 @@ __device__ void op_dense_mfma(C* __restrict__ lds, int T, const DevOp& op, const
 {
     using R = typename std::conditional<sizeof(C) == 8, float, double>::type;
     using Acc = typename std::conditional<sizeof(C) == 8, floatx4, doublex4>::type;
-    const R* __restrict__ A = reinterpret_cast<const R*>(Araw);
+    const C* __restrict__ Ac = reinterpret_cast<const C*>(Araw);
     constexpr int D = 1 << K, R2 = 2 * D, RB = R2 / 16, KS = R2 / 4;
     // the wave index is uniform: saying so keeps the block loop's bookkeeping and each
     // block's group base on the scalar unit
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     const int q = lane >> 4, col = lane & 15;
+    // A slot (rb, ks) of this lane is real-embedded entry (row 16 rb + i, column 4 ks + q),
+    // i = lane % 16.  Input column 4 ks + q is the real (ks even) or imaginary (ks odd)
+    // part of complex input 4 (ks / 2) + q, the order in which each lane feeds its complex
+    // inputs.  Rows are arranged so that output element e of lane 16 q + col is (complex
+    // row 8 rb + 2 q + e / 2, real / imaginary e % 2) in both precisions: the FP32
+    // instruction returns row i = 4 q + e there, so row i <-> (i / 2, i % 2); the FP64 one
+    // returns row i = 4 e + q (measured on gfx950), so row i <-> (2 (i % 4) + i / 8,
+    // (i / 4) % 2).  The entry is Re where the row's and column's real / imaginary halves
+    // agree (co == ks % 2), else -Im (co = 0) or +Im (co = 1); slots 2 j and 2 j + 1 share
+    // one complex entry.
+    const int i16 = lane & 15;
+    const int ro = sizeof(C) == 8 ? (i16 >> 1) : 2 * (i16 & 3) + (i16 >> 3);
+    const bool co = sizeof(C) == 8 ? (i16 & 1) : ((i16 >> 2) & 1);
+    const C* __restrict__ Al = Ac + ro * D + q;
     R a[RB][KS];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) a[rb][ks] = A[(rb * KS + ks) * 64 + lane];
+        for (int j = 0; j < KS / 2; ++j) {
+            const C u = Al[8 * rb * D + 4 * j];
+            a[rb][2 * j] = co ? u.y : u.x;
+            a[rb][2 * j + 1] = co ? u.x : -u.y;
+        }
     // this lane's row offsets (the same for every block)
     // (swizzled LDS positions: the lane's group and row parts are folded into rin / rout)
     const int bcol = swz<C>(group_base<K>(col, op));

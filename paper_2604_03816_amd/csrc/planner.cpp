@@ -53,9 +53,9 @@ PlanOpts default_opts(int dtype)
         o.sigma = 8;
         o.mfma_min_k = 3;
         o.fp32_mfma = true;
-        o.mfma_lds_floats = 4096;  // 16 KiB: room for every 3- and 4-qubit op of a pass on
-                                   // matrix cores (a VALU 4-qubit op costs more than the
-                                   // workgroup the larger block can cost in occupancy)
+        o.mfma_lds_floats = 2048;  // 8 KiB: room for every 3- and 4-qubit op of a pass on
+                                   // matrix cores (complex entries: 2 KiB per 4-qubit op)
+                                   // with four workgroups per CU (32 KiB tiles)
     } else {            // complex128: 16-byte amplitudes
         o.tile_qubits = 12;
         o.low_qubits = 3;   // 8 contiguous amplitudes: 128-byte runs, as complex64's 16
@@ -161,36 +161,6 @@ double op_cost(const FGate& g, const PlanOpts& o)
 }
 
 namespace {
-
-// Real-embedded 2D x 2D matrix of a dense complex D x D op, laid out as the A operands
-// of 16x16x4 MFMA steps: entry ((rb * KS + ks) * 64 + lane) is A[16 rb + i][4 ks + lane
-// / 16] with i = lane % 16.  Input column kk <-> (element 4 (kk / 8) + kk % 4, real/imag
-// (kk / 4) % 2), the order in which the kernel feeds each lane's complex inputs.  Output
-// rows are ordered so that output element e of lane q * 16 + col is (complex row 8 rb +
-// 2 q + e / 2, real/imag e % 2) in both precisions: the FP32 instruction returns row i
-// = 4 q + e there, so row i <-> (i / 2, i % 2); the FP64 instruction returns row i = 4 e
-// + q (measured on gfx950), so row i <-> (2 (i % 4) + i / 8, (i / 4) % 2).
-std::vector<double> mfma_operand(const std::vector<cd>& m, int k, bool fp64)
-{
-    const int D = 1 << k, R2 = 2 * D, RB = R2 / 16, KS = R2 / 4;
-    std::vector<double> out((size_t)R2 * R2);
-    for (int rb = 0; rb < RB; ++rb)
-        for (int ks = 0; ks < KS; ++ks)
-            for (int lane = 0; lane < 64; ++lane) {
-                const int i = lane % 16, kk = 4 * ks + lane / 16;
-                const int ro = 8 * rb + (fp64 ? 2 * (i % 4) + i / 8 : i / 2);
-                const int co = fp64 ? (i / 4) % 2 : i % 2;
-                const int ri = 4 * (kk / 8) + kk % 4, ci = (kk / 4) % 2;
-                const cd u = m[(size_t)ro * D + ri];
-                double v;
-                if (co == 0 && ci == 0) v = u.real();
-                else if (co == 0 && ci == 1) v = -u.imag();
-                else if (co == 1 && ci == 0) v = u.imag();
-                else v = u.real();
-                out[(size_t)(rb * KS + ks) * 64 + lane] = v;
-            }
-    return out;
-}
 
 bool is_identity(const FGate& g)
 {
@@ -834,23 +804,26 @@ void build_device_tables(HostPlan& P)
             if (g.kind == OP_DENSE) {
                 P.pool.insert(P.pool.end(), g.m.begin(), g.m.end());
                 ++P.dense_ops;
-                // (2 * 2^k)^2 operand entries: FP32 for complex64, FP64 (two floats' worth
-                // of bits each, 16-byte aligned) for complex128
-                const int per = dtype == 0 ? 1 : 2;
-                const int af = per * (4 << (2 * g.k));
+                // the matrix for the matrix cores: 2^k x 2^k complex entries, row-major, in
+                // the state's precision as raw floats (the kernel builds the real
+                // embedding in registers), 16-byte aligned
+                const int per = dtype == 0 ? 2 : 4;
+                const int af = per * (1 << (2 * g.k));
                 const int at = (a.a_len + 3) & ~3;
                 if (o.mfma_min_k > 0 && g.k >= o.mfma_min_k && g.k <= kMaxMfmaK && (1 << (a.m - g.k)) >= 16 &&
                     at + af <= o.mfma_lds_floats) {
-                    const std::vector<double> A = mfma_operand(g.m, g.k, dtype != 0);
                     P.apool.resize((size_t)a.a_off + at, 0.0f);
                     d.aoff = at;
-                    for (const double v : A) {
+                    for (const cd& v : g.m) {
                         if (dtype == 0) {
-                            P.apool.push_back((float)v);
+                            P.apool.push_back((float)v.real());
+                            P.apool.push_back((float)v.imag());
                         } else {
-                            float w[2];
-                            std::memcpy(w, &v, 8);
-                            P.apool.insert(P.apool.end(), w, w + 2);
+                            const double re = v.real(), im = v.imag();
+                            float w[4];
+                            std::memcpy(w, &re, 8);
+                            std::memcpy(w + 2, &im, 8);
+                            P.apool.insert(P.apool.end(), w, w + 4);
                         }
                     }
                     a.a_len = at + af;
