@@ -313,6 +313,17 @@ struct ElemGroup {
     size_t off;             // first double of this group's partials
 };
 
+// Two-state weights of a Pauli term with phase i^q: i^q for even parity, -i^q for odd.
+void set_pauli_weights(TermArgs& t, int i, int q)
+{
+    static const double re[4] = {1, 0, -1, 0}, im[4] = {0, 1, 0, -1};
+    q &= 3;
+    t.kw[i][0] = re[q];
+    t.kw[i][1] = im[q];
+    t.kw[i][2] = -re[q];
+    t.kw[i][3] = -im[q];
+}
+
 bool plan_elements(int n, const std::vector<PTerm>& terms, bool imag, std::vector<ElemGroup>& G, size_t& doubles,
                    std::string& err, int dtype, int xgrid = 4096)
 {
@@ -380,6 +391,7 @@ bool plan_elements(int n, const std::vector<PTerm>& terms, bool imag, std::vecto
             E.ta.zloc[i] = zl;
             E.ta.zglob[i] = (long long)zg;
             E.ta.ny[i] = p.ny + (imag ? 3 : 0);   // Im z = Re(-i z), and -i = i^3
+            set_pauli_weights(E.ta, i, E.ta.ny[i]);
         }
         if (g < zgroups) {
             // signs and lookups of the Z kernel (see ZTermArgs)
@@ -1500,6 +1512,12 @@ qsv_status qsv_adjoint_grad(int n, qsv_dtype dtype, const qsv_op* ops, size_t n_
         std::vector<long long> fixed;   // fixed gates undone first (descending time)
         std::vector<long long> ops;     // the layer's rotations (descending time)
         std::vector<ElemGroup> G;
+        // Evaluated before the previous layer's rotations are undone (their undo joins
+        // the next step's): each rotation's generator is then conjugated by the previous
+        // layer's rotation on its qubit, conj[l] >= 0 naming that RZ (or -1: none, or
+        // nothing to conjugate)
+        bool deferred = false;
+        std::vector<long long> conj;
     };
     std::vector<Layer> layers;
     size_t partial_doubles = 0;
@@ -1541,23 +1559,52 @@ qsv_status qsv_adjoint_grad(int n, qsv_dtype dtype, const qsv_op* ops, size_t n_
             for (size_t r = 0; r < rest.size(); ++r)
                 if (!take[r]) keep.push_back(rest[r]);
             rest.swap(keep);
-            std::vector<PTerm> gterms(Ly.ops.size());
-            for (size_t l = 0; l < Ly.ops.size(); ++l) {
-                const qsv_op& o = ops[Ly.ops[l]];
-                const unsigned long long bit = 1ull << o.targets[0];
-                PTerm t;
-                if (o.kind == 1) t.x = bit;                               // X
-                else if (o.kind == 2) { t.x = bit; t.z = bit; t.ny = 1; }  // Y
-                else t.z = bit;                                            // Z
-                t.coeff = 1.0;
-                gterms[l] = t;
-            }
-            size_t d = 0;
-            if (!plan_elements(n, gterms, true, Ly.G, d, err, dtype, 1024)) return fail(QSV_E_UNSUPPORTED, err);
-            for (ElemGroup& E : Ly.G) E.off += partial_doubles;
-            partial_doubles += d;
             layers.push_back(std::move(Ly));
         }
+    }
+    // A layer with no fixed gates of its own after it can be evaluated while the
+    // previous layer's rotations are still applied, when each of its generators either
+    // commutes with the previous layer's rotation on its qubit or is X or Y under an RZ
+    // there: RZ(t) X RZ(t)^+ = cos t X + sin t Y and RZ(t) Y RZ(t)^+ = cos t Y - sin t X,
+    // one partner product per amplitude with weights that depend on t.  The previous
+    // layer's undo then joins the next step's plan (one round of passes fewer per pair of
+    // layers).  No chains: the layer after a deferred one is evaluated as usual.
+    for (size_t li = 1; li < layers.size(); ++li) {
+        Layer& Ly = layers[li];
+        const Layer& Pv = layers[li - 1];
+        if (!Ly.fixed.empty() || Pv.deferred) continue;
+        std::vector<long long> on(n, -1);   // the previous layer's rotation on each qubit
+        for (const long long k : Pv.ops) on[ops[k].targets[0]] = k;
+        bool ok = true;
+        std::vector<long long> conj(Ly.ops.size(), -1);
+        for (size_t l = 0; l < Ly.ops.size() && ok; ++l) {
+            const qsv_op& o = ops[Ly.ops[l]];
+            const long long pk = on[o.targets[0]];
+            if (pk < 0) continue;
+            if (ops[pk].kind != 3) ok = false;       // only RZ conjugations are taken
+            else if (o.kind != 3) conj[l] = pk;      // X or Y generator under an RZ
+        }
+        if (!ok) continue;
+        Ly.deferred = true;
+        Ly.conj.swap(conj);
+    }
+    for (Layer& Ly : layers) {
+        std::vector<PTerm> gterms(Ly.ops.size());
+        for (size_t l = 0; l < Ly.ops.size(); ++l) {
+            const qsv_op& o = ops[Ly.ops[l]];
+            const unsigned long long bit = 1ull << o.targets[0];
+            PTerm t;
+            if (o.kind == 1) t.x = bit;                               // X
+            else if (o.kind == 2) { t.x = bit; t.z = bit; t.ny = 1; }  // Y
+            else t.z = bit;                                            // Z
+            if (Ly.deferred && Ly.conj[l] >= 0) t.z = bit;             // parity-weighted X / Y pair
+            t.coeff = 1.0;
+            gterms[l] = t;
+        }
+        size_t d = 0;
+        if (!plan_elements(n, gterms, true, Ly.G, d, err, dtype, 1024)) return fail(QSV_E_UNSUPPORTED, err);
+        for (ElemGroup& E : Ly.G) E.off += partial_doubles;
+        partial_doubles += d;
     }
 
     // the energy's matrix elements <phi|P_t|phi>: their partials follow the layers'
@@ -1617,7 +1664,10 @@ qsv_status qsv_adjoint_grad(int n, qsv_dtype dtype, const qsv_op* ops, size_t n_
     // whose matrices break a template's structure is planned from scratch.
     std::vector<std::vector<long long>> undo(layers.size());
     for (size_t li = 0; li < layers.size(); ++li) {
-        if (li > 0) undo[li] = layers[li - 1].ops;
+        if (layers[li].deferred) continue;   // evaluated before the previous layer's undo
+        if (li > 1 && layers[li - 1].deferred)
+            undo[li] = layers[li - 2].ops;   // the undo the deferred layer left behind
+        if (li > 0) undo[li].insert(undo[li].end(), layers[li - 1].ops.begin(), layers[li - 1].ops.end());
         undo[li].insert(undo[li].end(), layers[li].fixed.begin(), layers[li].fixed.end());
     }
     auto gates_of = [&](const std::vector<long long>& idx, const double* th, bool inverse) {
@@ -1675,7 +1725,28 @@ qsv_status qsv_adjoint_grad(int n, qsv_dtype dtype, const qsv_op* ops, size_t n_
                 if ((s2 = plan_for(undo_tmpl[li], gates_of(undo[li], th, true), hp)) != QSV_OK) return s2;
                 if ((s2 = enqueue_plan(phi, hp, lam)) != QSV_OK) return s2;   // one launch per pass, both states
             }
-            he = launch_elements(dtype, lam->buf, phi->buf, layers[li].G, lam->d_work, lam->stream);
+            const Layer& Ly = layers[li];
+            if (Ly.deferred) {   // generators conjugated by this vector's RZ angles
+                std::vector<ElemGroup> G = Ly.G;
+                for (ElemGroup& E : G)
+                    for (int i = 0; i < E.ta.nterms; ++i) {
+                        const size_t l = (size_t)E.idx[i];
+                        if (Ly.conj[l] < 0) continue;
+                        const double t = th[ops[Ly.conj[l]].param], c = std::cos(t), sn = std::sin(t);
+                        // Im <lambda|P'|phi> per element: Re(k conj(lambda[e ^ x]) phi[e]),
+                        // k by the parity of e's bit on the qubit
+                        const bool ygen = ops[Ly.ops[l]].kind == 2;
+                        const double k0r = ygen ? c : sn, k0i = ygen ? sn : -c;
+                        const double k1r = ygen ? -c : -sn, k1i = k0i;
+                        E.ta.kw[i][0] = k0r;
+                        E.ta.kw[i][1] = k0i;
+                        E.ta.kw[i][2] = k1r;
+                        E.ta.kw[i][3] = k1i;
+                    }
+                he = launch_elements(dtype, lam->buf, phi->buf, G, lam->d_work, lam->stream);
+            } else {
+                he = launch_elements(dtype, lam->buf, phi->buf, Ly.G, lam->d_work, lam->stream);
+            }
             if (he != hipSuccess) return fail(QSV_E_DEVICE, std::string("adjoint: ") + hipGetErrorString(he));
         }
         if (hipMemcpyAsync(lam->h_work, lam->d_work, pbytes, hipMemcpyDeviceToHost, lam->stream) != hipSuccess)

@@ -698,6 +698,7 @@ __global__ __launch_bounds__(kThreads) void k_norm(const float4* __restrict__ st
 struct TermRow {
     int x, z, q, pad;
     long long g;
+    double k[4];   // two-state weights (see TermArgs::kw)
 };
 
 template <typename C, int NS, bool TWO>
@@ -785,17 +786,23 @@ __device__ __forceinline__ void expval_tiles(gptr<C> __restrict__ sa, gptr<C> __
                         const double v = phase_re(ae, ae, q);
                         val += (__popc(e & z) & 1) ? -v : v;
                     }
-                } else {
-                    // per element: the partner from LDS, b[e] from this thread's registers
+                } else if (TWO) {
+                    // per element: the partner from LDS, b[e] from this thread's registers,
+                    // the weight by the parity of e's Z/Y bits (the bits outside the tile
+                    // swap the two weights for the whole tile)
+                    const double k0r = gneg ? rows[i].k[2] : rows[i].k[0], k0i = gneg ? rows[i].k[3] : rows[i].k[1];
+                    const double k1r = gneg ? rows[i].k[0] : rows[i].k[2], k1i = gneg ? rows[i].k[1] : rows[i].k[3];
 #pragma unroll
                     for (int j = 0; j < NS; ++j) {
                         const int e = (j << kLogThreads) | tid;
                         const C ap = tla[e ^ x];
-                        const double v = phase_re(ap, bv[j], q);
-                        val += (__popc(e & z) & 1) ? -v : v;
+                        const double wr = (double)ap.x * (double)bv[j].x + (double)ap.y * (double)bv[j].y;
+                        const double wi = (double)ap.x * (double)bv[j].y - (double)ap.y * (double)bv[j].x;
+                        const bool odd = __popc(e & z) & 1;
+                        val += (odd ? k1r : k0r) * wr - (odd ? k1i : k0i) * wi;
                     }
                 }
-                acc[i] += gneg ? -val : val;
+                acc[i] += (!TWO && gneg) ? -val : val;
             }
         }
         __syncthreads();   // the next tile overwrites LDS
@@ -818,7 +825,7 @@ __global__ __launch_bounds__(kThreads) void k_expval(const C* __restrict__ sa, c
     __shared__ TermRow rows[kMaxTermsPerLaunch];
     if (threadIdx.x < t.nterms) {
         const int i = threadIdx.x;
-        rows[i] = TermRow{t.xloc[i], t.zloc[i], t.ny[i] & 3, 0, t.zglob[i]};
+        rows[i] = TermRow{t.xloc[i], t.zloc[i], t.ny[i] & 3, 0, t.zglob[i], {t.kw[i][0], t.kw[i][1], t.kw[i][2], t.kw[i][3]}};
     }
     __syncthreads();
     double acc[kMaxTermsPerLaunch];
@@ -965,9 +972,14 @@ __global__ __launch_bounds__(kThreads) void k_expval_small(const C* __restrict__
             const C be = TWO ? sb[e] : sa[e];
             const double re = (double)ap.x * (double)be.x + (double)ap.y * (double)be.y;
             const double im = (double)ap.x * (double)be.y - (double)ap.y * (double)be.x;
-            const int q = t.ny[i] & 3;
-            val = (q == 0) ? re : (q == 1) ? -im : (q == 2) ? -re : im;
-            if (__popc(e & t.zloc[i]) & 1) val = -val;
+            const bool odd = __popc(e & t.zloc[i]) & 1;
+            if (TWO) {   // the two-state weights (TermArgs::kw)
+                val = (odd ? t.kw[i][2] : t.kw[i][0]) * re - (odd ? t.kw[i][3] : t.kw[i][1]) * im;
+            } else {
+                const int q = t.ny[i] & 3;
+                val = (q == 0) ? re : (q == 1) ? -im : (q == 2) ? -re : im;
+                if (odd) val = -val;
+            }
         }
         const NSum r = block_reduce(NSum{val, 0.0}, scratch);
         if (threadIdx.x == 0) {

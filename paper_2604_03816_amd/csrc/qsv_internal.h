@@ -64,6 +64,11 @@ struct TermArgs {
     int zloc[kMaxTermsPerLaunch];          // Z/Y support inside the tile, local bit mask
     long long zglob[kMaxTermsPerLaunch];   // Z/Y support outside the tile, physical mask
     int ny[kMaxTermsPerLaunch];            // number of Y factors (phase i^ny)
+    // Two-state kernel only: term i adds Re(k conj(a[e ^ x]) b[e]) per element e, with
+    // k = (kw[i][0], kw[i][1]) where e's bits in the Z/Y support have even parity and
+    // (kw[i][2], kw[i][3]) where odd.  A Pauli term has k = i^q and -i^q (q = ny, plus 3
+    // for the imaginary part); other weights give sums of two Paulis that share x and z.
+    double kw[kMaxTermsPerLaunch][4];
 };
 
 // Work list of the Z-only expectation kernel (every term's X/Y mask is zero).  The

@@ -110,6 +110,36 @@ def test_mixed_rotations_fixed_gates_and_shared_parameters(qsv):
     assert G[7] == 0.0
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_generators_under_rz_and_layer_orders(qsv, dtype):
+    """Layers evaluated before the previous layer's RZ rotations are undone (X and Y
+    generators conjugated by them, and RZ generators that commute with them), next to
+    layers that cannot be (an RY after the rotation on its qubit, fixed gates between
+    layers): every order against the oracle's parameter shift, in both precisions."""
+    n = 8
+    tpl, p = [], 0
+    for rep in range(3):
+        for q in range(n):   # X and Y generators, then RZ on most qubits
+            tpl.append(C.Op("RX" if q % 2 else "RY", (q,), param=p)); p += 1
+        for q in range(n - 1):
+            tpl.append(C.Op("RZ", (q,), param=p)); p += 1
+        if rep == 1:         # an RY after an RZ on one qubit, RZ after RZ on another
+            tpl.append(C.Op("RY", (2,), param=p)); p += 1
+            tpl.append(C.Op("RZ", (3,), param=p)); p += 1
+        for q in range(0, n - 1, 2):
+            tpl.append(C.Op("CZ", (q, q + 1)))
+        if rep == 0:         # a fixed gate with nothing after it but rotations
+            tpl.append(C.Op("H", (n - 1,)))
+    terms = C.tfim_terms(n)
+    params = np.random.default_rng(17).uniform(-np.pi, np.pi, size=(2, p))
+    E, G = qsv.adjoint_grad(n, tpl, params, terms, dtype)
+    for b in range(2):
+        e_ref = oracle.energy(n, tpl, params[b], terms)
+        g_ref = oracle.param_shift_grad(n, tpl, params[b], terms)
+        assert abs(E[b] - e_ref) <= (1e-12 if dtype == "c128" else 1e-4) * max(1.0, abs(e_ref))
+        assert rel(G[b], g_ref) <= REL[dtype], rel(G[b], g_ref)
+
+
 def test_autograd_function(qsv):
     import torch
     from paper_2604_03816_amd.autograd import AdjointExpval
