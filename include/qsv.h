@@ -334,8 +334,12 @@ typedef struct {
  * dE_b/dtheta_j by the adjoint method (one forward sweep, one reverse sweep that
  * uncomputes the state and the co-state layer by layer).  params: host, B x P
  * row-major doubles.  energy: host, B doubles; grad: host, B x P doubles (entries of
- * parameters no op uses are 0).  Runs on `stream` (hipStream_t, NULL = default) and
- * synchronises it.  Errors: QSV_E_ARG, QSV_E_OOM, QSV_E_DEVICE. */
+ * parameters no op uses are 0).  Runs on `stream` (hipStream_t, NULL = default) and, for
+ * B > 1, on a second stream of its own that first waits for the work already queued on
+ * `stream` (consecutive parameter vectors alternate between the two, each with its own
+ * pair of state buffers); returns when both are done.  Temporary device memory: four
+ * states of n_qubits (two when B = 1 or when the second pair does not fit).  Errors:
+ * QSV_E_ARG, QSV_E_OOM, QSV_E_DEVICE. */
 qsv_status qsv_adjoint_grad(int n_qubits, qsv_dtype dtype, const qsv_op* ops, size_t n_ops,
                             const double* params, int B, int P,
                             const qsv_pauli_term* H, size_t n_terms,
