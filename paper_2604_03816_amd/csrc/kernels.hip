@@ -278,8 +278,9 @@ __device__ void op_dense(C* __restrict__ lds, int T, const DevOp& op, cptr<C> __
 // (A[i][k] sits in lane i + 16 k and B[k][j] in lane j + 16 k in both precisions; the
 // output rows' order differs between the FP32 and FP64 instructions, which the planner's
 // lanes' choice of A rows absorbs).  The op's complex matrix is staged in LDS once per
-// pass, D x D row-major in the state's precision (half the bytes of its real embedding
-// [[Re, -Im], [Im, Re]]); each lane reads the complex entries of its A-operand slots
+// pass, D x D in the state's precision (half the bytes of its real embedding
+// [[Re, -Im], [Im, Re]]), each row's entries permuted for the LDS banks; each lane reads
+// the complex entries of its A-operand slots
 // once per op and keeps the real-embedded values in registers for the whole op.  All
 // reads of a block precede its writes, so the update is in place; waves own disjoint
 // groups.
@@ -309,13 +310,15 @@ __device__ void op_dense_mfma(C* __restrict__ lds, int T, const DevOp& op, const
     const int i16 = lane & 15;
     const int ro = sizeof(C) == 8 ? (i16 >> 1) : 2 * (i16 & 3) + (i16 >> 3);
     const bool co = sizeof(C) == 8 ? (i16 & 1) : ((i16 >> 2) & 1);
-    const C* __restrict__ Al = Ac + ro * D + q;
+    // entry (r, c) is staged at r D + (c ^ (r % 8)), so that the eight rows a group of
+    // lanes reads in one access fall in different LDS banks
+    const C* __restrict__ Al = Ac + ro * D;
     R a[RB][KS];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int j = 0; j < KS / 2; ++j) {
-            const C u = Al[8 * rb * D + 4 * j];
+            const C u = Al[8 * rb * D + ((4 * j + q) ^ ro)];
             a[rb][2 * j] = co ? u.y : u.x;
             a[rb][2 * j + 1] = co ? u.x : -u.y;
         }

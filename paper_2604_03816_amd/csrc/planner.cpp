@@ -804,17 +804,20 @@ void build_device_tables(HostPlan& P)
             if (g.kind == OP_DENSE) {
                 P.pool.insert(P.pool.end(), g.m.begin(), g.m.end());
                 ++P.dense_ops;
-                // the matrix for the matrix cores: 2^k x 2^k complex entries, row-major, in
-                // the state's precision as raw floats (the kernel builds the real
-                // embedding in registers), 16-byte aligned
+                // the matrix for the matrix cores: 2^k x 2^k complex entries, entry (r, c) at
+                // r 2^k + (c ^ (r % 8)) (the kernel's reads then spread over the LDS
+                // banks), in the state's precision as raw floats (the kernel builds the
+                // real embedding in registers), 16-byte aligned
                 const int per = dtype == 0 ? 2 : 4;
-                const int af = per * (1 << (2 * g.k));
+                const int af = per * dd * dd;
                 const int at = (a.a_len + 3) & ~3;
                 if (o.mfma_min_k > 0 && g.k >= o.mfma_min_k && g.k <= kMaxMfmaK && (1 << (a.m - g.k)) >= 16 &&
                     at + af <= o.mfma_lds_floats) {
                     P.apool.resize((size_t)a.a_off + at, 0.0f);
                     d.aoff = at;
-                    for (const cd& v : g.m) {
+                    for (int e = 0; e < dd * dd; ++e) {
+                        const int r = e / dd, c = (e % dd) ^ (r & 7);
+                        const cd v = g.m[(size_t)r * dd + c];
                         if (dtype == 0) {
                             P.apool.push_back((float)v.real());
                             P.apool.push_back((float)v.imag());
