@@ -1330,15 +1330,21 @@ hipError_t launch_pass_t(void* st, void* st2, const PassArgs& a, long long ntile
 template <typename C, bool WIDE>
 static hipError_t launch_batch_pass_t(const BatchItem* items, const int* count, int grid, size_t lds, hipStream_t s)
 {
-    static bool set = false;
-    if (!set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_batch_pass<C, WIDE>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
-        if (e != hipSuccess) return e;
-        set = true;
-    }
     hipLaunchKernelGGL((k_batch_pass<C, WIDE>), dim3(grid), dim3(kThreads), lds, s, items, count);
     return hipGetLastError();
+}
+
+// The batched pass kernels may take more than the default 64 KiB of dynamic LDS; the
+// limit is raised once, outside any stream capture (the server's step is captured).
+hipError_t prepare_batch_pass()
+{
+    const void* fns[4] = {(const void*)k_batch_pass<float2, true>, (const void*)k_batch_pass<float2, false>,
+                          (const void*)k_batch_pass<double2, true>, (const void*)k_batch_pass<double2, false>};
+    for (const void* f : fns) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 98304);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_batch_pass(int dtype, const BatchItem* items, const int* count, int grid, int tile_qubits,

@@ -142,6 +142,7 @@ __host__ __device__ constexpr int kMaxTileQubitsC(int dt) { return dt == 0 ? 13 
 // Launchers (kernels.hip).  dtype 0 = complex64, 1 = complex128.
 // wide = false: the variant without the register-heavy op paths (every item's pass must
 // be free of them: HostPlan::pwide).
+hipError_t prepare_batch_pass();   // raises the batched kernels' LDS limit; call before capturing them
 hipError_t launch_batch_pass(int dtype, const BatchItem* items, const int* count, int grid, int tile_qubits,
                              hipStream_t s, bool wide);
 hipError_t launch_zsum_batch(int dtype, const ZItem* items, const int* count, double* partial, int grid,

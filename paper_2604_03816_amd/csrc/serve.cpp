@@ -42,7 +42,7 @@ bool read_gate_public(const qsv_gate& g, int n, InGate& out, std::string& err);
 namespace {
 
 constexpr int kZQ = 12;   // chunk qubits of the batched <Z> reduction (k_zsum_batch)
-constexpr int kServeTileQubits[2] = {12, 11};   // 32 KiB tiles: complex64, complex128
+constexpr int kServeTileQubits[2] = {12, 12};   // 2^12-amplitude tiles (32 / 64 KiB), as the plain path
 
 struct Req {
     long long id = 0;
@@ -372,6 +372,11 @@ qsv_status qsv_server_create(const qsv_server_opts* opts, void* stream, qsv_serv
         }
         s->own_stream = true;
     }
+    if (!s->o.dry_run && prepare_batch_pass() != hipSuccess) {
+        if (s->own_stream) (void)hipStreamDestroy(s->stream);
+        delete s;
+        return set_error(QSV_E_DEVICE, "batched pass kernel set-up failed");
+    }
     const int P = s->o.passes_per_step;
     const int slots = s->o.max_slots;
     if (s->o.dry_run) {
@@ -472,8 +477,8 @@ qsv_status qsv_server_submit(qsv_server s, int n, qsv_dtype dtype, const qsv_gat
     r->dtype = dtype;
     std::string oerr;
     if (!plan_opts_from(dtype, popts, r->popts, oerr)) return set_error(QSV_E_ARG, oerr);
-    // served tiles are capped so every batched launch needs at most 32 KiB of LDS per
-    // workgroup (several workgroups per CU)
+    // served tiles are capped at 2^12 amplitudes (the batched launch sizes its LDS for
+    // that tile plus the capped operand block)
     const int cap = kServeTileQubits[dtype];
     r->popts.tile_qubits = std::min(r->popts.tile_qubits, cap);
     r->popts.whole_state_max = std::min(r->popts.whole_state_max, cap);
