@@ -26,9 +26,10 @@ struct DevOp {
     int off;            // offset into the complex pool: dense 4^k, diagonal 2^k, permutation 2^k phases
     int ioff;           // permutation: offset into the int pool (2^k source rows)
     int flags;          // permutation: 1 when some phase differs from 1
-    int aoff;           // float offset inside the pass's operand block in LDS, else -1: a complex64
-                        // dense op on MFMA (its real-embedded matrix in MFMA operand order) or a
-                        // diagonal op (its 2^k phases, bit copies of the pool entries)
+    int aoff;           // float offset inside the pass's operand block in LDS, else -1: a dense
+                        // op on matrix cores (its 2^k x 2^k complex matrix in the state's
+                        // precision, entries of row r permuted by c ^ (r % 8)) or a diagonal op
+                        // (its 2^k phases, bit copies of the pool entries)
 };
 
 // Everything a pass kernel needs to place its tile in the state vector.
