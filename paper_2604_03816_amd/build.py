@@ -27,7 +27,7 @@ SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=und
              "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined",
              "-shared-libsan", "-O1"]
 
-SOURCES = ["kernels.hip", "planner.cpp", "capi.cpp", "serve.cpp", "noalloc.hip"]
+SOURCES = ["kernels.hip", "planner.cpp", "capi.cpp", "serve.cpp", "noalloc.hip", "sample_sort.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

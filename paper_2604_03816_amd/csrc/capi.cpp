@@ -1124,36 +1124,6 @@ struct DevBuf {
 
 }  // namespace
 
-// Indices of the uniforms in increasing order of value, equal values in index order: an
-// LSD radix sort on the IEEE-754 bit patterns (monotone for non-negative doubles), 16
-// bits per pass, a pass skipped when every key has the same digit.
-static void order_uniforms(const double* u, long long n, std::vector<long long>& order)
-{
-    std::vector<uint64_t> key((size_t)n), k2((size_t)n);
-    std::vector<long long> idx((size_t)n), i2((size_t)n);
-    for (long long i = 0; i < n; ++i) {
-        const double v = u[i] == 0.0 ? 0.0 : u[i];   // -0.0 (accepted as 0) sorts as +0.0
-        std::memcpy(&key[i], &v, sizeof(double));
-        idx[i] = i;
-    }
-    std::vector<size_t> cnt(65537);
-    for (int pass = 0; pass < 4; ++pass) {
-        const int sh = 16 * pass;
-        std::fill(cnt.begin(), cnt.end(), 0);
-        for (long long i = 0; i < n; ++i) ++cnt[((key[i] >> sh) & 0xFFFF) + 1];
-        if (n > 0 && cnt[((key[0] >> sh) & 0xFFFF) + 1] == (size_t)n) continue;
-        for (int d = 0; d < 65536; ++d) cnt[d + 1] += cnt[d];
-        for (long long i = 0; i < n; ++i) {
-            const size_t p = cnt[(key[i] >> sh) & 0xFFFF]++;
-            k2[p] = key[i];
-            i2[p] = idx[i];
-        }
-        key.swap(k2);
-        idx.swap(i2);
-    }
-    order.swap(idx);
-}
-
 qsv_status qsv_sample(qsv_state s, const int* qubits, int m, const double* uniforms, long long shots,
                       long long* out)
 {
@@ -1208,10 +1178,20 @@ qsv_status qsv_sample(qsv_state s, const int* qubits, int m, const double* unifo
     const double P = Cp[nchunks];
     if (lastnz < 0 || !(P > 0)) return fail(QSV_E_ARG, "the state has no probability mass");
 
-    // shots in increasing order of u; each goes to the chunk whose prefix interval holds
-    // u * P, with its residual inside that chunk
-    std::vector<long long> order;
-    order_uniforms(uniforms, shots, order);
+    // shots in increasing order of u (sorted on the device, equal values in index order);
+    // each goes to the chunk whose prefix interval holds u * P, with its residual inside
+    // that chunk
+    std::vector<long long> order((size_t)shots);
+    {
+        DevBuf du, dorder, dscratch;
+        const size_t sb = sort_uniforms_scratch(shots);
+        if (!du.alloc(sizeof(double) * shots) || !dorder.alloc(sizeof(long long) * shots) || !dscratch.alloc(sb))
+            return fail(QSV_E_OOM, "sampling buffer allocation failed");
+        QSV_HIP(hipMemcpyAsync(du.p, uniforms, sizeof(double) * shots, hipMemcpyHostToDevice, s->stream));
+        QSV_HIP(sort_uniforms((const double*)du.p, shots, (long long*)dorder.p, dscratch.p, sb, s->stream));
+        QSV_HIP(hipMemcpyAsync(order.data(), dorder.p, sizeof(long long) * shots, hipMemcpyDeviceToHost, s->stream));
+        QSV_HIP(hipStreamSynchronize(s->stream));
+    }
     std::vector<double> res(shots);
     std::vector<SampleChunk> list;
     long long c = 0;

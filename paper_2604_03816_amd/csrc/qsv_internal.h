@@ -143,6 +143,11 @@ __host__ __device__ constexpr int kMaxTileQubitsC(int dt) { return dt == 0 ? 13 
 // Launchers (kernels.hip).  dtype 0 = complex64, 1 = complex128.
 // wide = false: the variant without the register-heavy op paths (every item's pass must
 // be free of them: HostPlan::pwide).
+// qsv_sample's shot order: order (device, n) = 0..n-1 sorted stably by the uniforms u
+// (device, n values in [0, 1)); scratch: device memory of sort_uniforms_scratch(n) bytes.
+size_t sort_uniforms_scratch(long long n);
+hipError_t sort_uniforms(const double* u, long long n, long long* order, void* scratch, size_t scratch_bytes,
+                         hipStream_t s);
 hipError_t prepare_batch_pass();   // raises the batched kernels' LDS limit; call before capturing them
 hipError_t launch_batch_pass(int dtype, const BatchItem* items, const int* count, int grid, int tile_qubits,
                              hipStream_t s, bool wide);
