@@ -488,9 +488,9 @@ def adjoint_bench(args):
 def sampling_bench(args, ops):
     """Measurement sampling (inverse transform of the Born distribution) on the headline
     state: the 30-qubit brickwork in complex64, 2^20 shots over all qubits and over 8
-    qubits; uniforms from seed 8.  Wall time of the synchronous call (the shots sorted on the
-    device, one chunk-total pass over the state, the shots' chunks found on the host, one
-    pass over the chunks that hold shots)."""
+    qubits; uniforms from seed 8.  Wall time of the synchronous call (one chunk-total pass
+    over the state, prefix sums on the host; on the device the shots sorted, assigned to
+    chunks and grouped, one pass over the chunks that hold shots)."""
     import numpy as np
     import torch
     from paper_2604_03816_amd import qsv

@@ -1178,44 +1178,32 @@ qsv_status qsv_sample(qsv_state s, const int* qubits, int m, const double* unifo
     const double P = Cp[nchunks];
     if (lastnz < 0 || !(P > 0)) return fail(QSV_E_ARG, "the state has no probability mass");
 
-    // shots in increasing order of u (sorted on the device, equal values in index order);
+    // On the device: the shots in increasing order of u (equal values in index order);
     // each goes to the chunk whose prefix interval holds u * P, with its residual inside
-    // that chunk
-    std::vector<long long> order((size_t)shots);
-    {
-        DevBuf du, dorder, dscratch;
-        const size_t sb = sort_uniforms_scratch(shots);
-        if (!du.alloc(sizeof(double) * shots) || !dorder.alloc(sizeof(long long) * shots) || !dscratch.alloc(sb))
-            return fail(QSV_E_OOM, "sampling buffer allocation failed");
-        QSV_HIP(hipMemcpyAsync(du.p, uniforms, sizeof(double) * shots, hipMemcpyHostToDevice, s->stream));
-        QSV_HIP(sort_uniforms((const double*)du.p, shots, (long long*)dorder.p, dscratch.p, sb, s->stream));
-        QSV_HIP(hipMemcpyAsync(order.data(), dorder.p, sizeof(long long) * shots, hipMemcpyDeviceToHost, s->stream));
-        QSV_HIP(hipStreamSynchronize(s->stream));
-    }
-    std::vector<double> res(shots);
-    std::vector<SampleChunk> list;
-    long long c = 0;
-    while (c < lastnz && S[c] <= 0) ++c;
-    for (long long k = 0; k < shots; ++k) {
-        const double t = uniforms[order[k]] * P;
-        while (c < lastnz && (t >= Cp[c + 1] || S[c] <= 0)) ++c;
-        res[k] = t - Cp[c];
-        if (list.empty() || list.back().chunk != c) list.push_back(SampleChunk{c, k, k + 1});
-        else list.back().hi = k + 1;
-    }
-    DevBuf dlist, dres, dout;
-    if (!dlist.alloc(sizeof(SampleChunk) * list.size()) || !dres.alloc(sizeof(double) * shots) ||
-        !dout.alloc(sizeof(long long) * shots))
+    // that chunk; shots of one chunk form a run, resolved together by one workgroup
+    long long c0 = 0;
+    while (c0 < lastnz && S[c0] <= 0) ++c0;
+    DevBuf du, dorder, dscratch, dcum, dres, dlist, dnruns, dgot, dout;
+    const size_t sb = std::max(sort_uniforms_scratch(shots), sample_assign_scratch(shots));
+    if (!du.alloc(sizeof(double) * shots) || !dorder.alloc(sizeof(long long) * shots) || !dscratch.alloc(sb) ||
+        !dcum.alloc(sizeof(double) * (nchunks + 1)) || !dres.alloc(sizeof(double) * shots) ||
+        !dlist.alloc(sizeof(SampleChunk) * std::min<long long>(shots, nchunks)) || !dnruns.alloc(sizeof(long long)) ||
+        !dgot.alloc(sizeof(long long) * shots) || !dout.alloc(sizeof(long long) * shots))
         return fail(QSV_E_OOM, "sampling buffer allocation failed");
-    std::vector<long long> got(shots);
-    QSV_HIP(hipMemcpyAsync(dlist.p, list.data(), sizeof(SampleChunk) * list.size(), hipMemcpyHostToDevice,
-                           s->stream));
-    QSV_HIP(hipMemcpyAsync(dres.p, res.data(), sizeof(double) * shots, hipMemcpyHostToDevice, s->stream));
-    QSV_HIP(launch_sample_chunks(sdt, src, cb, (const SampleChunk*)dlist.p, (long long)list.size(),
-                                 (const double*)dres.p, (long long*)dout.p, s->stream));
-    QSV_HIP(hipMemcpyAsync(got.data(), dout.p, sizeof(long long) * shots, hipMemcpyDeviceToHost, s->stream));
+    QSV_HIP(hipMemcpyAsync(du.p, uniforms, sizeof(double) * shots, hipMemcpyHostToDevice, s->stream));
+    QSV_HIP(hipMemcpyAsync(dcum.p, Cp.data(), sizeof(double) * (nchunks + 1), hipMemcpyHostToDevice, s->stream));
+    QSV_HIP(sort_uniforms((const double*)du.p, shots, (long long*)dorder.p, dscratch.p, sb, s->stream));
+    QSV_HIP(sample_assign((const double*)du.p, (const long long*)dorder.p, shots, (const double*)dcum.p, c0, lastnz, P,
+                          (double*)dres.p, (SampleChunk*)dlist.p, (long long*)dnruns.p, dscratch.p, sb, s->stream));
+    long long nruns = 0;
+    QSV_HIP(hipMemcpyAsync(&nruns, dnruns.p, sizeof(long long), hipMemcpyDeviceToHost, s->stream));
     QSV_HIP(hipStreamSynchronize(s->stream));
-    for (long long k = 0; k < shots; ++k) out[order[k]] = got[k];
+    QSV_HIP(launch_sample_chunks(sdt, src, cb, (const SampleChunk*)dlist.p, nruns, (const double*)dres.p,
+                                 (long long*)dgot.p, s->stream));
+    QSV_HIP(scatter_outcomes((const long long*)dorder.p, (const long long*)dgot.p, shots, (long long*)dout.p,
+                             s->stream));
+    QSV_HIP(hipMemcpyAsync(out, dout.p, sizeof(long long) * shots, hipMemcpyDeviceToHost, s->stream));
+    QSV_HIP(hipStreamSynchronize(s->stream));
     return QSV_OK;
 }
 

@@ -186,6 +186,14 @@ hipError_t launch_chunk_totals(int src_dtype, const void* src, int chunk_bits, l
                                hipStream_t s);
 hipError_t launch_sample_chunks(int src_dtype, const void* src, int chunk_bits, const SampleChunk* list,
                                 long long nlist, const double* residual, long long* outcome, hipStream_t s);
+// qsv_sample's assignment of the sorted shots to chunks (residual per shot, the runs of
+// equal chunks as a SampleChunk list, their number in *nruns, all device memory; scratch
+// of sample_assign_scratch(n) bytes) and the final scatter out[order[k]] = got[k].
+size_t sample_assign_scratch(long long n);
+hipError_t sample_assign(const double* u, const long long* order, long long n, const double* cum, long long c0,
+                         long long lastnz, double P, double* residual, SampleChunk* list, long long* nruns,
+                         void* scratch, size_t scratch_bytes, hipStream_t s);
+hipError_t scatter_outcomes(const long long* order, const long long* got, long long n, long long* out, hipStream_t s);
 hipError_t launch_probs_marg(int dtype, const void* st, const MargArgs& a, double* partial, double* out,
                              hipStream_t s, bool density = false);
 hipError_t launch_dm_pauli(int dtype, const void* st, int n, const PauliSumArgs& p, int grid, double* partial,
