@@ -103,6 +103,24 @@ def test_repeated_uniforms_zero_and_top(qsv, dtype):
     s.free()
 
 
+@pytest.mark.parametrize("shots", [1, 2, 3, 257])
+def test_few_shots_and_single_runs(qsv, shots):
+    """The device groups sorted shots into runs of one chunk: one shot, a few shots in
+    one or several chunks, and all shots in one chunk (a basis state) against the oracle."""
+    n = 18
+    s = qsv.State(n, "c128")
+    s.apply(C.brickwork(n, 4, 30))
+    psi = s.get()
+    u = np.random.default_rng(40 + shots).random(shots)
+    assert check_against_oracle(psi, None, u, s.sample(u)) == 1.0
+    assert check_against_oracle(psi, [17, 2], u, s.sample(u, [17, 2])) == 1.0
+    z = np.zeros(1 << n, complex)
+    z[12345] = 1.0
+    s.set(z)
+    assert np.all(s.sample(u) == 12345)
+    s.free()
+
+
 def test_frequencies_match_probabilities(qsv):
     n = 12
     s = qsv.State(n, "c64")
