@@ -393,6 +393,92 @@ __device__ void op_dense_mfma(C* __restrict__ lds, int T, const DevOp& op, const
     }
 }
 
+// 4-qubit dense op on matrix cores with three real products instead of the four of
+// the real embedding (Gauss's form of a complex product).  With M = Ar + i Ai and an
+// input column x = xr + i xi, t = Ar (xr + xi) gives Re(M x) = t - (Ar + Ai) xi and
+// Im(M x) = t + (Ai - Ar) xr: per block of 16 groups three 16 x 16 x 16 real products,
+// 12 matrix-core instructions where the real embedding takes 16.  Lane (q, col) =
+// (lane / 16, lane % 16) feeds complex input row 4 j + q of group col at step j and
+// holds row col of each A operand (A[i][k] sits in lane i + 16 k); output element e is
+// complex row 4 q + e (FP32 instruction) or 4 e + q (FP64).  The staged operand is the
+// one op_dense_mfma reads (entry (r, c) at 16 r + (c ^ (r % 8))); each lane forms its
+// three A values per step from one complex entry.
+template <typename C, int NT = kThreads>
+__device__ void op_dense_mfma_3m(C* __restrict__ lds, int T, const DevOp& op, const float* __restrict__ Araw)
+{
+    using R = typename std::conditional<sizeof(C) == 8, float, double>::type;
+    using Acc = typename std::conditional<sizeof(C) == 8, floatx4, doublex4>::type;
+    constexpr int K = 4, D = 16;
+    const C* __restrict__ Ac = reinterpret_cast<const C*>(Araw);
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int q = lane >> 4, col = lane & 15;
+    const C* __restrict__ Al = Ac + col * D;
+    R ar[4], an[4], as[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const C u = Al[(4 * j + q) ^ (col & 7)];
+        ar[j] = u.x;
+        an[j] = -(u.x + u.y);
+        as[j] = u.y - u.x;
+    }
+    const int bcol = swz<C>(group_base<K>(col, op));
+    int rin[4], rout[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        rin[j] = swz<C>(row_off<K>(4 * j + q, op)) ^ bcol;
+        rout[j] = swz<C>(row_off<K>(sizeof(C) == 8 ? 4 * q + j : 4 * j + q, op)) ^ bcol;
+    }
+    const int nblk = (T >> K) >> 4;
+    // complex64: two blocks per iteration, as in op_dense_mfma
+    constexpr int NW = NT / 64, U = sizeof(C) == 8 ? 2 : 1;
+    auto mfma = [](R a, R b, Acc c) {
+        if constexpr (sizeof(C) == 8) return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+        else return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    };
+    for (int blk = wave; blk < nblk; blk += U * NW) {
+        int sb[U];
+        bool live[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int b = blk + u * NW;
+            live[u] = b < nblk;   // uniform
+            sb[u] = __builtin_amdgcn_readfirstlane(swz<C>(group_base<K>((live[u] ? b : blk) << 4, op)));
+        }
+        C v[U][4];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[u][j] = lds[sb[u] ^ rin[j]];
+        Acc t[U], yr[U], yi[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) t[u] = Acc{0, 0, 0, 0};
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int u = 0; u < U; ++u) t[u] = mfma(ar[j], v[u][j].x + v[u][j].y, t[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) yr[u] = yi[u] = t[u];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                yr[u] = mfma(an[j], v[u][j].y, yr[u]);
+                yi[u] = mfma(as[j], v[u][j].x, yi[u]);
+            }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (!live[u]) continue;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                C o;
+                o.x = yr[u][e];
+                o.y = yi[u][e];
+                lds[sb[u] ^ rout[e]] = o;
+            }
+        }
+    }
+}
+
 template <typename C, int K, int NT = kThreads>
 __device__ void op_perm(C* __restrict__ lds, int T, const DevOp& op, cptr<C> __restrict__ ph,
                         cptr<int> __restrict__ src)
@@ -460,7 +546,7 @@ __device__ __forceinline__ void apply_ops(C* __restrict__ lds, int T, cptr<DevOp
         if (op.kind == OP_DENSE && op.aoff >= 0) {
             // the planner gives matrix cores 3- and 4-qubit ops only (kMaxMfmaK)
             if (op.k == 3) op_dense_mfma<C, 3, NT>(lds, T, op, alds + op.aoff);
-            else if (op.k == 4) op_dense_mfma<C, 4, NT>(lds, T, op, alds + op.aoff);
+            else if (op.k == 4) op_dense_mfma_3m<C, NT>(lds, T, op, alds + op.aoff);
             lds_sync();
             continue;
         }

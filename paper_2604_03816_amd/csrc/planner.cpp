@@ -53,6 +53,7 @@ PlanOpts default_opts(int dtype)
         o.sigma = 8;
         o.mfma_min_k = 3;
         o.fp32_mfma = true;
+        o.amp_floats = 2;
         o.mfma_lds_floats = 2048;  // 8 KiB: room for every 3- and 4-qubit op of a pass on
                                    // matrix cores (complex entries: 2 KiB per 4-qubit op)
                                    // with four workgroups per CU (32 KiB tiles)
@@ -62,6 +63,7 @@ PlanOpts default_opts(int dtype)
         o.whole_state_max = 12;
         o.pass_budget = 320;
         o.sigma = 8;
+        o.amp_floats = 4;
         o.mfma_min_k = 3;          // FP64 matrix cores: no faster than FP64 VALU in peak,
         o.mfma_lds_floats = 4096;  // but free of the VALU path's per-row scalar loads
     }
@@ -155,9 +157,17 @@ double op_fma(const FGate& g)
 double op_cost(const FGate& g, const PlanOpts& o)
 {
     const double f = op_fma(g);
-    if (g.kind == OP_DENSE && o.fp32_mfma && o.mfma_min_k > 0 && g.k >= o.mfma_min_k && g.k <= kMaxMfmaK)
-        return 0.5 * f;
+    if (mfma_eligible(g, o)) {
+        // matrix cores: complex64 at twice the FP32 VALU rate; a 4-qubit op takes three
+        // real products where the real embedding of a 3-qubit one takes four
+        return (o.fp32_mfma ? 0.5 : 1.0) * (g.k == 4 ? 0.75 : 1.0) * f;
+    }
     return f;
+}
+
+bool mfma_eligible(const FGate& g, const PlanOpts& o)
+{
+    return g.kind == OP_DENSE && o.mfma_min_k > 0 && g.k >= o.mfma_min_k && g.k <= kMaxMfmaK;
 }
 
 namespace {
@@ -636,6 +646,7 @@ PassPlan build_pass(int n, const std::vector<FGate>& fused, const std::vector<ch
         blocked_d &= ~blocked;
     };
     double budget = o.pass_budget;
+    int afl = 0;   // operand floats staged so far, as the device tables stage them
     for (int i = 0; i < F; ++i) {
         if (done[i]) continue;
         const FGate& g = fused[i];
@@ -645,6 +656,12 @@ PassPlan build_pass(int n, const std::vector<FGate>& fused, const std::vector<ch
         if ((gm & blocked) || (gm & ~gd & blocked_d)) { defer(gm, gd); continue; }
         const double c = op_cost(g, o) + o.sigma;
         const bool limit_ops = o.max_ops_per_pass > 0 && (int)pp.ops.size() >= o.max_ops_per_pass;
+        // a matrix-core op whose operand no longer fits the pass's block would run on the
+        // VALU at several times its planned cost: it waits for the next pass instead
+        // (diagonal tables are staged too, where they fit)
+        const bool mf = mfma_eligible(g, o);
+        const int af = mf ? o.amp_floats << (2 * g.k) : g.kind == OP_DIAG ? o.amp_floats << g.k : 0;
+        const bool fits_operands = whole || !mf || ((afl + 3) & ~3) + af <= o.mfma_lds_floats || pp.ops.empty();
         const bool fits_budget = whole || o.pass_budget < 0 || c <= budget || pp.ops.empty();
         unsigned long long nA = (g.kind == OP_DIAG) ? A : (A | gm);
         if (grow && pp.ops.empty() && __builtin_popcountll(nA) > m) {
@@ -654,11 +671,12 @@ PassPlan build_pass(int n, const std::vector<FGate>& fused, const std::vector<ch
             nA = A | gm;
         }
         const bool fits_tile = grow ? __builtin_popcountll(nA) <= m : nA == A;
-        if (!limit_ops && fits_budget && fits_tile) {
+        if (!limit_ops && fits_budget && fits_operands && fits_tile) {
             A = nA;
             pp.ops.push_back(i);
             budget -= c;
             pp.cost += c;
+            if (af > 0 && ((afl + 3) & ~3) + af <= o.mfma_lds_floats) afl = ((afl + 3) & ~3) + af;
         } else {
             defer(gm, gd);
             if ((blocked & all) == all) break;

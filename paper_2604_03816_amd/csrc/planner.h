@@ -49,6 +49,7 @@ struct PlanOpts {
     bool fp32_mfma = false;    // complex64: MFMA at twice the VALU rate (cost halved in planning)
     int mfma_lds_floats = 2048;  // per-pass cap of operand floats staged in LDS (MFMA matrices,
                                  // diagonal tables)
+    int amp_floats = 2;        // floats per staged complex entry (2: complex64, 4: complex128)
 };
 
 struct PassPlan {
@@ -93,8 +94,13 @@ double op_fma(const FGate& g);
 
 // Scheduling cost of one op on chip (excluding sigma): op_fma, halved for complex64 dense
 // ops that run on FP32 MFMA (twice the non-packed VALU rate; FP64 MFMA has the FP64 VALU
-// rate, so complex128 costs are unchanged).
+// rate), and times 3/4 for 4-qubit dense ops on matrix cores (three real products per
+// block instead of four).
 double op_cost(const FGate& g, const PlanOpts& o);
+
+// A dense op of o.mfma_min_k .. kMaxMfmaK qubits: it runs on matrix cores when its
+// operand fits the pass's LDS operand block.
+bool mfma_eligible(const FGate& g, const PlanOpts& o);
 
 // Physical qubits on which a fused gate is diagonal: target q[j] counts when every entry
 // coupling rows and columns that differ in local bit j is exactly zero.

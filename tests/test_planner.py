@@ -290,10 +290,12 @@ def test_fusion_modes_and_matrix_core_option():
     assert fused["mfma_ops"] > 0 and fused["mfma_fma_per_amp"] > 0
     no_mc = qsv.Plan(n, "c64", ops, matrix_cores=-1).stats()
     assert no_mc["mfma_ops"] == 0 and no_mc["mfma_fma_per_amp"] == 0
-    # complex128 runs them on FP64 matrix cores; the planner's costs stay those of the VALU
+    # complex128 runs them on FP64 matrix cores, at the FP64 VALU's rate except for 4-qubit
+    # ops (three real products instead of four), which the planner then fuses more readily
     m128 = qsv.Plan(n, "c128", ops).stats()
     assert m128["mfma_ops"] > 0
-    assert qsv.Plan(n, "c128", ops, matrix_cores=-1).stats()["fused_out"] == m128["fused_out"]
+    v128 = qsv.Plan(n, "c128", ops, matrix_cores=-1).stats()
+    assert v128["mfma_ops"] == 0 and v128["fused_out"] >= m128["fused_out"]
     for bad in ({"fuse": 3}, {"fuse": -1}, {"matrix_cores": 2}, {"matrix_cores": 5}, {"matrix_cores": 6}, {"matrix_cores": -2}):
         with pytest.raises(qsv.QSVError):
             qsv.Plan(n, "c64", ops, **bad)
