@@ -11,7 +11,10 @@ FP32 arithmetic; the same circuit in complex128 is reported beside it.
 
 value = fused gates x 2 x 2^n x bytes-per-amplitude / step time  ("fused-gate amplitude
 GB/s": every fused gate must read and write each amplitude once; several fused gates
-share one HBM round trip, so the figure can exceed the HBM peak).
+share one HBM round trip, so the figure can exceed the HBM peak).  Because it counts
+the planner's fused gates, a plan that fuses into fewer, wider gates lowers it even when
+the step gets faster; detail.gate_amplitude_GB_per_s counts the circuit's own gates
+instead (the same for every plan), and ms_per_step compares plans directly.
 
 roofline: the pass kernel, bound by HBM bandwidth.  Algorithmic bytes per launch = 2 x
 2^n x bytes-per-amplitude (one read and one write of the state; the first pass, which
@@ -172,6 +175,7 @@ def run_dtype(torch, qsv, C, args, dtype, ops, terms):
     elem = 8 if dtype == "c64" else 16
     pass_bytes = 2.0 * (2 ** n) * elem
     value = st["fused_out"] * pass_bytes / sec / 1e9
+    gate_value = st["gates_in"] * pass_bytes / sec / 1e9
     # algorithmic bytes per launch, averaged over the step's launches: every pass reads and
     # writes the state once, except the first, which builds |0...0> on chip and only writes
     npass = st["passes"]
@@ -198,6 +202,7 @@ def run_dtype(torch, qsv, C, args, dtype, ops, terms):
     norm = state.norm()
     out = {
         "value": value,
+        "gate_amplitude_GB_per_s": gate_value,
         "ms_per_step": sec * 1e3,
         "plan_ms": plan_ms,
         "gates": st["gates_in"],
@@ -702,14 +707,16 @@ def main():
                    "state": "complex64"},
         "roofline": main_rec["roofline"],
         "hbm_frac": main_rec["hbm"]["frac"],
-        "detail": {k: main_rec[k] for k in ("plan_ms", "avg_pass_ms", "norm_minus_1", "hbm", "alu")},
+        "detail": {k: main_rec[k] for k in ("gate_amplitude_GB_per_s", "plan_ms", "avg_pass_ms", "norm_minus_1",
+                                            "hbm", "alu")},
     }
     if probe is not None:
         rec["copy_probe"] = probe
     if not args.no_c128:
         r = run_dtype(torch, qsv, C, args, "c128", ops, terms)
         progress("complex128 step done")
-        rec["c128"] = {"value": r["value"], "unit": "GB/s", "dtype": "f64", "ms_per_step": r["ms_per_step"],
+        rec["c128"] = {"value": r["value"], "gate_amplitude_GB_per_s": r["gate_amplitude_GB_per_s"], "unit": "GB/s",
+                       "dtype": "f64", "ms_per_step": r["ms_per_step"],
                        "fused_gates": r["fused_gates"], "passes": r["passes"], "avg_pass_ms": r["avg_pass_ms"],
                        "roofline": r["roofline"], "hbm": r["hbm"], "alu": r["alu"],
                        "norm_minus_1": r["norm_minus_1"]}
