@@ -159,10 +159,16 @@ double op_cost(const FGate& g, const PlanOpts& o)
     const double f = op_fma(g);
     if (mfma_eligible(g, o)) {
         // matrix cores: complex64 at twice the FP32 VALU rate; a 4-qubit op takes three
-        // real products where the real embedding of a 3-qubit one takes four
-        return (o.fp32_mfma ? 0.5 : 1.0) * (g.k == 4 ? 0.75 : 1.0) * f;
+        // real products where the real embedding of a 3-qubit one takes four (priced so
+        // only where a pass can stage four of them)
+        return (o.fp32_mfma ? 0.5 : 1.0) * (g.k == 4 && wide_operand_block(o) ? 0.75 : 1.0) * f;
     }
     return f;
+}
+
+bool wide_operand_block(const PlanOpts& o)
+{
+    return o.mfma_lds_floats >= 4 * (o.amp_floats << 8);
 }
 
 bool mfma_eligible(const FGate& g, const PlanOpts& o)
@@ -200,22 +206,50 @@ std::vector<cd> embed(const std::vector<cd>& a, const int* qa, int ka, const int
         return s;
     };
     const int da = 1 << ka;
+    if (ka == kq) return a;   // a spans Q: its targets are Q itself, in the same order
+    int sr[1 << kMaxK];
+    for (int r = 0; r < dq; ++r) sr[r] = sub(r);
     std::vector<cd> e((size_t)dq * dq, cd(0, 0));
     for (int r = 0; r < dq; ++r)
         for (int c = 0; c < dq; ++c)
-            if ((r & ~amask) == (c & ~amask)) e[(size_t)r * dq + c] = a[(size_t)sub(r) * da + sub(c)];
+            if ((r & ~amask) == (c & ~amask)) e[(size_t)r * dq + c] = a[(size_t)sr[r] * da + sr[c]];
     return e;
 }
 
-std::vector<cd> matmul(const std::vector<cd>& A, const std::vector<cd>& B, int d)
+// E(v) . B for a dq x dq matrix B over the ascending qubit list Q, without forming E(v):
+// row r of the product mixes the rows of B that differ from r only in v's bits, in
+// ascending order: the sums of the plain product E(v) B, term for term (zero entries
+// of E(v) skipped).
+std::vector<cd> apply_left(const std::vector<cd>& vm, const int* qv, int kv, const int* Q, int kq,
+                           const std::vector<cd>& B)
 {
-    std::vector<cd> C((size_t)d * d, cd(0, 0));
-    for (int i = 0; i < d; ++i)
-        for (int l = 0; l < d; ++l) {
-            const cd a = A[(size_t)i * d + l];
-            if (a == cd(0, 0)) continue;
-            for (int j = 0; j < d; ++j) C[(size_t)i * d + j] += a * B[(size_t)l * d + j];
+    const int dq = 1 << kq, dv = 1 << kv;
+    int pos[kMaxK], vmask = 0;
+    for (int j = 0; j < kv; ++j) {
+        int p = 0;
+        while (Q[p] != qv[j]) ++p;
+        pos[j] = p;
+        vmask |= 1 << p;
+    }
+    int spread[1 << kMaxK];
+    for (int a = 0; a < dv; ++a) {
+        int x = 0;
+        for (int j = 0; j < kv; ++j) x |= ((a >> j) & 1) << pos[j];
+        spread[a] = x;
+    }
+    std::vector<cd> C((size_t)dq * dq, cd(0, 0));
+    for (int r = 0; r < dq; ++r) {
+        int ra = 0;
+        for (int j = 0; j < kv; ++j) ra |= ((r >> pos[j]) & 1) << j;
+        const int base = r & ~vmask;
+        cd* out = &C[(size_t)r * dq];
+        for (int a = 0; a < dv; ++a) {
+            const cd w = vm[(size_t)ra * dv + a];
+            if (w == cd(0, 0)) continue;
+            const cd* in = &B[(size_t)(base | spread[a]) * dq];
+            for (int c = 0; c < dq; ++c) out[c] += w * in[c];
         }
+    }
     return C;
 }
 
@@ -314,10 +348,8 @@ FGate fuse_pair(const FGate& u, const FGate& v, int kmax, bool& ok)
     std::sort(Q, Q + kq);
     f.k = kq;
     for (int j = 0; j < kq; ++j) f.q[j] = Q[j];
-    const int d = 1 << kq;
-    const std::vector<cd> eu = embed(u.m, u.q, u.k, Q, kq);
-    const std::vector<cd> ev = embed(v.m, v.q, v.k, Q, kq);
-    f.m = matmul(ev, eu, d);  // Eq. 9: U_fused = U_v . U_u (u applied first)
+    // Eq. 9: U_fused = U_v . U_u (u applied first)
+    f.m = apply_left(v.m, v.q, v.k, Q, kq, embed(u.m, u.q, u.k, Q, kq));
     f.kind = classify(f.m, kq);
     f.dq = diag_qubit_mask(f);
     f.first = std::min(u.first, v.first);
@@ -417,8 +449,8 @@ void run_fusion(std::vector<Node>& nodes, const PlanOpts& o)
                         S.prev[slot_of(S, x)] = u;
                     }
                 }
-                U.g = f;
-                for (int j = 0; j < f.k; ++j) {
+                U.g = std::move(f);
+                for (int j = 0; j < U.g.k; ++j) {
                     U.prev[j] = nprev[j];
                     U.next[j] = nnext[j];
                 }
@@ -658,10 +690,13 @@ PassPlan build_pass(int n, const std::vector<FGate>& fused, const std::vector<ch
         const bool limit_ops = o.max_ops_per_pass > 0 && (int)pp.ops.size() >= o.max_ops_per_pass;
         // a matrix-core op whose operand no longer fits the pass's block would run on the
         // VALU at several times its planned cost: it waits for the next pass instead
-        // (diagonal tables are staged too, where they fit)
+        // (diagonal tables are staged too, where they fit).  With a block too small for
+        // four 4-qubit matrices (served complex128 passes) that would cost more passes
+        // than the VALU fallback: there the op stays in the pass.
         const bool mf = mfma_eligible(g, o);
         const int af = mf ? o.amp_floats << (2 * g.k) : g.kind == OP_DIAG ? o.amp_floats << g.k : 0;
-        const bool fits_operands = whole || !mf || ((afl + 3) & ~3) + af <= o.mfma_lds_floats || pp.ops.empty();
+        const bool fits_operands = whole || !mf || !wide_operand_block(o) ||
+                                   ((afl + 3) & ~3) + af <= o.mfma_lds_floats || pp.ops.empty();
         const bool fits_budget = whole || o.pass_budget < 0 || c <= budget || pp.ops.empty();
         unsigned long long nA = (g.kind == OP_DIAG) ? A : (A | gm);
         if (grow && pp.ops.empty() && __builtin_popcountll(nA) > m) {

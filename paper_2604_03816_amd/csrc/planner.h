@@ -95,8 +95,12 @@ double op_fma(const FGate& g);
 // Scheduling cost of one op on chip (excluding sigma): op_fma, halved for complex64 dense
 // ops that run on FP32 MFMA (twice the non-packed VALU rate; FP64 MFMA has the FP64 VALU
 // rate), and times 3/4 for 4-qubit dense ops on matrix cores (three real products per
-// block instead of four).
+// block instead of four) when the pass's operand block holds four of them.
 double op_cost(const FGate& g, const PlanOpts& o);
+
+// The per-pass operand block holds at least four 4-qubit matrices (the planner's defaults
+// for both dtypes; not served complex128 passes, whose block is capped lower).
+bool wide_operand_block(const PlanOpts& o);
 
 // A dense op of o.mfma_min_k .. kMaxMfmaK qubits: it runs on matrix cores when its
 // operand fits the pass's LDS operand block.
