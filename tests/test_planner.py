@@ -511,3 +511,32 @@ def test_plan_refresh_refuses_what_it_cannot_refresh():
     with pytest.raises(qsv.QSVError) as e:
         ident.refresh([C.Op("X", (3,)), C.Op("Y", (3,)), C.Op("H", (1,))])
     assert e.value.status == 4
+
+
+def _is_permutation(m):
+    nz = np.abs(m) > 0
+    return bool(np.all(nz.sum(axis=0) == 1) and np.all(nz.sum(axis=1) == 1))
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_matrix_core_ops_fit_each_pass_operand_block(dtype):
+    # every 3- and 4-qubit dense op of a pass fits the pass's LDS operand block, so none
+    # falls back to the VALU; priced at three quarters, 4-qubit ops are what the fusion
+    # mostly makes on a brickwork
+    n = 24
+    ops = C.brickwork(n, 20, 3)
+    plan = qsv.Plan(n, dtype, ops)
+    st = plan.stats()
+    fused = plan.fused_gates()
+    dense = [len(q) for q, m, diag in fused if not diag and not _is_permutation(m)]
+    assert st["mfma_ops"] == sum(1 for k in dense if k in (3, 4))
+    assert sum(1 for k in dense if k == 4) > sum(1 for k in dense if k == 3)
+    per = 2 if dtype == "c64" else 4
+    block = 2048 if dtype == "c64" else 4096
+    for idx, _ in plan.passes():
+        used = 0
+        for i in idx:
+            q, m, diag = fused[i]
+            if not diag and not _is_permutation(m) and len(q) in (3, 4):
+                used = ((used + 3) & ~3) + per * 4 ** len(q)
+        assert used <= block
