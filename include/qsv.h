@@ -116,8 +116,11 @@ typedef struct {
                             Algorithm 2 (fuse whenever the width allows) */
     int tile_qubits;     /* log2 amplitudes per on-chip tile, 0 = default */
     int low_qubits;      /* contiguous low qubits kept in every tile, 0 = default */
-    double pass_budget;  /* per-pass arithmetic budget (FMA per amplitude), 0 = default,
-                            < 0 = unlimited */
+    double pass_budget;  /* per-pass arithmetic budget (FMA per amplitude: a dense op
+                            4 * 2^k, halved on complex64 matrix cores, times 3/4 for a
+                            4-qubit matrix-core op), 0 = default, < 0 = unlimited.  A pass
+                            also ends where its next matrix-core op's operand would not
+                            fit the pass's LDS operand block */
     int matrix_cores;    /* dense ops on >= this many (and at most 4) targets run on matrix
                             cores (MFMA; FP32 for complex64, FP64 for complex128) when their
                             operand block fits the pass's LDS budget: 0 = default (3),
