@@ -269,7 +269,8 @@ __device__ void op_dense(C* __restrict__ lds, int T, const DevOp& op, cptr<C> __
     }
 }
 
-// Dense op on matrix cores: FP32 MFMA for complex64, FP64 MFMA for complex128.  The op
+// Dense op on matrix cores: FP32 MFMA for complex64, FP64 MFMA for complex128 (the
+// 3-qubit ops; 4-qubit ones take op_dense_mfma_3m below).  The op
 // is the real-embedded 2D x 2D matrix (D = 2^K) times the tile viewed as D x (T / D)
 // complex columns (one column per group of amplitudes that differ only in the op's
 // targets).  A wave takes 16 groups at a time: lane (q, col) = (lane / 16, lane % 16)

@@ -159,8 +159,8 @@ double op_cost(const FGate& g, const PlanOpts& o)
     const double f = op_fma(g);
     if (mfma_eligible(g, o)) {
         // matrix cores: complex64 at twice the FP32 VALU rate; a 4-qubit op takes three
-        // real products where the real embedding of a 3-qubit one takes four (priced so
-        // only where a pass can stage four of them)
+        // real products where its real embedding would take four (priced so only where
+        // a pass can stage four of them)
         return (o.fp32_mfma ? 0.5 : 1.0) * (g.k == 4 && wide_operand_block(o) ? 0.75 : 1.0) * f;
     }
     return f;
@@ -859,8 +859,8 @@ void build_device_tables(HostPlan& P)
                 ++P.dense_ops;
                 // the matrix for the matrix cores: 2^k x 2^k complex entries, entry (r, c) at
                 // r 2^k + (c ^ (r % 8)) (the kernel's reads then spread over the LDS
-                // banks), in the state's precision as raw floats (the kernel builds the
-                // real embedding in registers), 16-byte aligned
+                // banks), in the state's precision as raw floats (the kernel forms its
+                // real operands in registers), 16-byte aligned
                 const int per = dtype == 0 ? 2 : 4;
                 const int af = per * dd * dd;
                 const int at = (a.a_len + 3) & ~3;
